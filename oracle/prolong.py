@@ -1,0 +1,184 @@
+"""Diffusion-free VEM prolongation (Sec. 4, "Diffusion-Free VEM Prolongation Operator").
+
+A fine DOF that coincides with a coarse DOF copies it.  Every other fine DOF
+is evaluated from the coarse function's projection on the lowest-dimensional
+coarse entity whose closure holds the DOF's support:
+* a coarse edge: the 1-D space is P_k(e) itself, so the projection is the
+  Lagrange interpolant through the edge's DOFs;
+* a coarse face: the 2-D projection Pi_f of the face's own DOFs;
+* a coarse cell: the 3-D projection Pi of the cell's DOFs.
+Point DOFs (vertices, edge midpoints) take the projection's value at the
+point; face-mean and cell-mean DOFs take its mean over the fine face / cell.
+Because every fine DOF of a fine cell inside coarse cell E depends on DOFs of
+E only, the Galerkin product couples only DOFs of one coarse cell.
+
+Reading for the set notation the paper leaves garbled: the new fine DOFs are
+split by the dimension of their host entity, which makes the edge, face and
+volume sets pairwise disjoint.  Coarse DOFs on a Dirichlet face are dropped
+(their value is zero).  Coarse DOFs that no fine DOF depends on (vertices in
+the solid part of a coarse cell) give zero columns; the caller drops them, so
+the coarse operators stay non-singular (reading: the paper asserts nested
+hierarchies avoid rank-deficient transfers).
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .geometry import polygon_area_vec
+from .quadrature import polygon_rule, polyhedron_rule
+from .vem import CellGeometry, cell_projector, face_projector
+
+TOL = 1e-9
+
+
+def _point_in_face(p, P, n, tol=TOL):
+    d = float(n @ P[0])
+    if abs(float(n @ p) - d) > tol:
+        return False
+    m = len(P)
+    Q = np.roll(P, -1, axis=0)
+    E = Q - P
+    on = np.stack([E[:, 1] * n[2] - E[:, 2] * n[1], E[:, 2] * n[0] - E[:, 0] * n[2],
+                   E[:, 0] * n[1] - E[:, 1] * n[0]], -1)
+    s = np.einsum("ij,ij->i", on, p - P)
+    return bool(np.all(s <= tol * np.sqrt((on ** 2).sum(1))))
+
+
+class CoarseLevel:
+    """Lazily computed projections of a coarse level."""
+
+    def __init__(self, mesh, dofs):
+        self.mesh, self.dofs = mesh, dofs
+        self.k = dofs.k
+        self._cell = {}
+        self._face = {}
+
+    def cell(self, c):
+        if c not in self._cell:
+            g = CellGeometry(self.mesh, c)
+            Pis, _, _ = cell_projector(g, self.k)
+            self._cell[c] = (g, Pis, self.dofs.cell_dofs(c))
+        return self._cell[c]
+
+    def face(self, f):
+        """(Pi_f*, frame, global coarse DOFs of the face in face-local order)."""
+        if f not in self._face:
+            m = self.mesh
+            cyc = m.faces[f]
+            P = m.X[cyc]
+            Pif, fr = face_projector(P, m.face_normal[f], self.k)
+            gd = list(cyc)
+            if self.k == 2:
+                nv, ne = self.dofs.nv, self.dofs.ne
+                for i in range(len(cyc)):
+                    a, b = cyc[i], cyc[(i + 1) % len(cyc)]
+                    gd.append(nv + m.edge_index[(a, b) if a < b else (b, a)])
+                gd.append(nv + ne + f)
+            self._face[f] = (Pif, fr, np.array(gd))
+        return self._face[f]
+
+
+def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
+    """P [fine free x coarse free] as scipy CSR, plus the host kind per fine DOF."""
+    k = fine_dofs.k
+    CL = coarse_level = CoarseLevel(coarse_mesh, coarse_dofs)
+    X, Xc = fine_mesh.X, coarse_mesh.X
+    nvf, nef, nff = fine_dofs.nv, fine_dofs.ne, fine_dofs.nf
+    rows = {}
+    host_kind = np.full(fine_dofs.n, -1, dtype=np.int8)
+
+    def point_row(p, E):
+        g, Pis, cd = CL.cell(E)
+        # coarse vertex
+        for v in g.verts:
+            if np.linalg.norm(Xc[v] - p) < TOL:
+                return {int(v): 1.0}, 0
+        # coarse edge
+        for e in g.edges:
+            a, b = coarse_mesh.edges[e]
+            pa, pb = Xc[a], Xc[b]
+            ab = pb - pa
+            tau = float((p - pa) @ ab / (ab @ ab))
+            if 0.0 < tau < 1.0 and np.linalg.norm(p - pa - tau * ab) < TOL:
+                if k == 1:
+                    return {int(a): 1.0 - tau, int(b): tau}, 1
+                mid = coarse_dofs.nv + e
+                return {int(a): 2 * (tau - 0.5) * (tau - 1.0), int(mid): -4.0 * tau * (tau - 1.0),
+                        int(b): 2.0 * tau * (tau - 0.5)}, 1
+        # coarse face
+        for f in g.face_ids:
+            P = Xc[coarse_mesh.faces[f]]
+            if _point_in_face(p, P, coarse_mesh.face_normal[f]):
+                Pif, fr, fd = CL.face(f)
+                w = fr.mono(p, k)[0] @ Pif
+                return dict(zip(fd.tolist(), w.tolist())), 2
+        w = g.basis.mono(p, k)[0] @ Pis
+        return dict(zip(cd.tolist(), w.tolist())), 3
+
+    def face_mean_row(fpts, E):
+        g, Pis, cd = CL.cell(E)
+        qp, qw = polygon_rule(fpts)
+        area_f = qw.sum()
+        fc = qw @ qp / area_f
+        nrm = polygon_area_vec(fpts)
+        for f in g.face_ids:
+            P = Xc[coarse_mesh.faces[f]]
+            n = coarse_mesh.face_normal[f]
+            if abs(abs(float(n @ nrm)) / np.linalg.norm(nrm) - 1.0) > 1e-9:
+                continue
+            if not _point_in_face(fc, P, n):
+                continue
+            qpc, qwc = polygon_rule(P)
+            if abs(qwc.sum() - area_f) < 1e-12 * area_f and \
+                    np.linalg.norm(qwc @ qpc / qwc.sum() - fc) < TOL:
+                return {int(coarse_dofs.nv + coarse_dofs.ne + f): 1.0}, 4
+            Pif, fr, fd = CL.face(f)
+            w = (qw @ fr.mono(qp, k) / area_f) @ Pif
+            return dict(zip(fd.tolist(), w.tolist())), 2
+        w = (qw @ g.basis.mono(qp, k) / area_f) @ Pis
+        return dict(zip(cd.tolist(), w.tolist())), 3
+
+    def cell_mean_row(c_f, E):
+        g, Pis, cd = CL.cell(E)
+        vol_f = fine_mesh.cell_volume[c_f]
+        if abs(vol_f - coarse_mesh.cell_volume[E]) < 1e-12 * vol_f and \
+                np.linalg.norm(fine_mesh.cell_centroid[c_f] - coarse_mesh.cell_centroid[E]) < TOL:
+            return {int(cd[-1]): 1.0}, 4
+        gf = CellGeometry(fine_mesh, c_f)
+        qp, qw = polyhedron_rule([X[c] for c in gf.faces], centre=X[gf.verts].mean(axis=0))
+        w = (qw @ g.basis.mono(qp, k) / qw.sum()) @ Pis
+        return dict(zip(cd.tolist(), w.tolist())), 3
+
+    for c in range(len(fine_mesh.cell_faces)):
+        E = int(parent[c])
+        fd = fine_dofs.cell_dofs(c)
+        for v in fine_mesh.cell_verts[c]:
+            if v not in rows:
+                rows[v], host_kind[v] = point_row(X[v], E)
+        if k == 2:
+            for e in fine_mesh.cell_edges[c]:
+                i = nvf + e
+                if i not in rows:
+                    a, b = fine_mesh.edges[e]
+                    rows[i], host_kind[i] = point_row(0.5 * (X[a] + X[b]), E)
+            for f in fine_mesh.cell_face_ids[c]:
+                i = nvf + nef + f
+                if i not in rows:
+                    rows[i], host_kind[i] = face_mean_row(X[fine_mesh.faces[f]], E)
+            i = nvf + nef + nff + c
+            rows[i], host_kind[i] = cell_mean_row(c, E)
+    r, cidx, val = [], [], []
+    for i, row in rows.items():
+        fi = fine_dofs.free[i]
+        if fi < 0:
+            continue
+        for j, w in row.items():
+            cj = coarse_dofs.free[j]
+            if cj < 0 or w == 0.0:
+                continue
+            r.append(fi)
+            cidx.append(cj)
+            val.append(w)
+    P = sp.csr_matrix((val, (r, cidx)), shape=(fine_dofs.n_free, coarse_dofs.n_free))
+    P.sum_duplicates()
+    P.sort_indices()
+    return P, host_kind

@@ -1,0 +1,184 @@
+/*
+ * fvem.h - C ABI of the FastVEM pressure-projection solver for MI355X (gfx950).
+ *
+ * The library solves the pressure system of the paper's VEM projection
+ * (Sec. 3.1: assemble K and r, solve K p = r; Sec. 3.2: r is the projected
+ * divergence of the first-order vertex velocity) with CG preconditioned by
+ * the paper's Galerkin geometric multigrid (Sec. 4: diffusion-free
+ * prolongation P, restriction R = P^T, coarse operators A_c = R A_f P).
+ *
+ * Conventions for every entry point:
+ *  - Every call returns an fvem_status and never throws across the ABI;
+ *    fvem_last_error() returns a thread-local message for the last failure.
+ *  - Host arrays passed in descriptors are owned by the caller and only read
+ *    during the call; the library keeps copies.
+ *  - Device pointers are HIP device memory on the device that was current
+ *    when the hierarchy was built; work is enqueued on the given stream
+ *    (NULL = the default stream) and is complete in stream order when the
+ *    call returns.
+ *  - Results are bitwise deterministic for a given input and build.
+ */
+#ifndef FVEM_H
+#define FVEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FVEM_OK = 0,
+    FVEM_ERR_INVALID = 1,        /* malformed descriptor or argument */
+    FVEM_ERR_HIP = 2,            /* a HIP runtime call failed; destroy the handle */
+    FVEM_ERR_OOM = 3,            /* device or host allocation failed */
+    FVEM_ERR_NOT_SPD = 4,        /* coarsest operator has a negative pivot */
+    FVEM_ERR_NOT_CONVERGED = 5,  /* maxit reached; outputs hold the last iterate */
+    FVEM_ERR_NONFINITE = 6,      /* NaN/Inf in the input or a CG breakdown */
+    FVEM_ERR_BUSY = 7            /* another solve is running on this handle */
+} fvem_status;
+
+/* Compressed sparse rows.  row_ptr has n_rows+1 entries (int64), col holds
+ * int32 column indices sorted within each row, val the FP64 values. */
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+} fvem_csr;
+
+/* One level of the nested hierarchy (level 0 = finest).
+ *  n_dof     free (unknown) DOFs of the level.
+ *  n_cells   cells of the level; cell c owns local DOFs
+ *            cell_dof[cell_ptr[c] .. cell_ptr[c+1]), each a free DOF index or
+ *            -1 for an eliminated DOF (Dirichlet, or a coarse DOF the
+ *            prolongation never uses).  Local order: vertices, edges, faces,
+ *            cell (Sec. 3.1 DOF list).
+ *  parent    [n_cells] index of the cell of level+1 containing each cell
+ *            (the hierarchy is nested, Sec. 5.2); NULL on the coarsest level.
+ *  P         prolongation from level+1 to this level, n_dof x n_dof(level+1),
+ *            diffusion-free: every row of a DOF of cell c may only reference
+ *            DOFs of cell parent[c] (Sec. 4); unused on the coarsest level. */
+typedef struct {
+    int64_t n_dof;
+    int64_t n_cells;
+    const int64_t *cell_ptr;
+    const int32_t *cell_dof;
+    const int32_t *parent;
+    fvem_csr P;
+} fvem_level_desc;
+
+/* The problem: hierarchy plus the finest level's element operators.
+ *  ke_ptr/ke_val  element stiffness K^E of each level-0 cell, row-major
+ *                 n_E x n_E over the cell's local DOFs (n_E = cell_ptr[c+1]
+ *                 - cell_ptr[c]); ke_ptr[c] is the offset of the block.
+ *  n_vert, cell_vptr/cell_vert  velocity vertices; cell c's vertices are
+ *                 cell_vert[cell_vptr[c] .. cell_vptr[c+1]).
+ *  be_ptr/be_val  divergence block B^E of each cell, row-major
+ *                 n_E x (3 n_vE): column 3 v + d is component d of the cell's
+ *                 v-th vertex velocity (Sec. 3.2 right-hand side).
+ *  component      [n_dof of level 0]: id of the pure-Neumann component of
+ *                 each free DOF (0 .. n_components-1), or -1 where the
+ *                 component is anchored by Dirichlet DOFs. */
+typedef struct {
+    int32_t n_levels;
+    const fvem_level_desc *levels;
+    const int64_t *ke_ptr;
+    const double *ke_val;
+    int64_t n_vert;
+    const int64_t *cell_vptr;
+    const int32_t *cell_vert;
+    const int64_t *be_ptr;
+    const double *be_val;
+    const int32_t *component;
+    int32_t n_components;
+} fvem_grid_desc;
+
+/* Hierarchy options.  Zero-initialised fields take the defaults in brackets. */
+typedef struct {
+    int32_t cheb_degree;        /* Chebyshev degree per smoothing [5] */
+    double cheb_lower;          /* lower end of the interval as a fraction of lmax [1/30] */
+    int32_t coarse_dense_max;   /* largest coarsest level factored densely [16384] */
+    double coarse_rcond;        /* pivots below rcond * diag are treated as zero [1e-10] */
+} fvem_options;
+
+typedef enum { FVEM_PREC_FP64 = 0, FVEM_PREC_MIXED = 1 } fvem_precision;
+typedef enum { FVEM_INPUT_VELOCITY = 0, FVEM_INPUT_RHS = 1 } fvem_input;
+
+typedef struct {
+    double tol;             /* stop when ||b - K x|| / ||b|| <= tol [1e-8] */
+    int32_t maxit;          /* [500] */
+    int32_t precision;      /* fvem_precision: FP32 V-cycle inside FP64 CG, or all FP64 */
+    int32_t input;          /* fvem_input */
+    int32_t replace_every;  /* true-residual replacement period [10] */
+    int32_t profile;        /* nonzero: time every finest-level Chebyshev launch (HIP events) */
+} fvem_solve_opts;
+
+typedef struct {
+    int32_t iterations;
+    double rel_residual;    /* true ||b - K x|| / ||b|| at exit (FP64) */
+    double ms_total;        /* device time of the call (HIP events) */
+    double ms_fine_smoother; /* with profile: summed device time of the finest-level
+                                fused Chebyshev-step launches (SpMV + update) */
+    int32_t n_fine_smoother; /* with profile: number of those launches */
+    int32_t n_levels;
+} fvem_solve_stats;
+
+typedef struct fvem_hierarchy fvem_hierarchy;
+
+/* Build the solver hierarchy on the current device (setup, Sec. 4).
+ * Assembles K from the element blocks, forms A_{l+1} = P_l^T A_l P_l
+ * element-wise per coarse cell, transposes P, computes Chebyshev bounds,
+ * FP32 copies and the coarsest-level factorisation, and preallocates every
+ * solve buffer.  Errors: INVALID (bad sizes, indices out of range, a P row
+ * that references a DOF outside its cell's parent, non-finite values), OOM,
+ * HIP, NOT_SPD.  On success *out owns all device memory. */
+fvem_status fvem_hierarchy_build(const fvem_grid_desc *g, const fvem_options *o,
+                                 void *hip_stream, fvem_hierarchy **out);
+
+/* Pressure solve.  in_dev: velocity [3 n_vert] (FVEM_INPUT_VELOCITY, b = B u)
+ * or right-hand side [n_dof0] (FVEM_INPUT_RHS).  p_dev: [n_dof0] output,
+ * zero DOF mean on every pure-Neumann component.  Returns NOT_CONVERGED
+ * (outputs and stats still written) when maxit is reached. */
+fvem_status fvem_solve(fvem_hierarchy *h, const double *in_dev, double *p_dev,
+                       const fvem_solve_opts *so, fvem_solve_stats *st, void *hip_stream);
+
+/* Adjoint of fvem_solve: given g_p [n_dof0], returns
+ * g_u = B^T P_perp K^+ P_perp g_p [3 n_vert] (FVEM_INPUT_VELOCITY) or
+ * g_b = P_perp K^+ P_perp g_p [n_dof0] (FVEM_INPUT_RHS).  K is symmetric
+ * (Sec. 3.1), so the same MG-PCG and hierarchy solve the adjoint system. */
+fvem_status fvem_solve_adjoint(fvem_hierarchy *h, const double *gp_dev, double *gu_dev,
+                               const fvem_solve_opts *so, fvem_solve_stats *st, void *hip_stream);
+
+/* Operators used by tests and loss plumbing (all FP64, device vectors). */
+typedef enum {
+    FVEM_OP_K = 0,        /* y[n_dof0] = K x[n_dof0] */
+    FVEM_OP_B = 1,        /* y[n_dof0] = B x[3 n_vert] */
+    FVEM_OP_BT = 2,       /* y[3 n_vert] = B^T x[n_dof0] */
+    FVEM_OP_VCYCLE = 3,   /* y[n_dof0] = M x: one V-cycle of the preconditioner (FP64) */
+    FVEM_OP_VCYCLE32 = 4, /* the same V-cycle with FP32 smoothing and transfers */
+    FVEM_OP_PROJECT = 5   /* y = P_perp x (zero mean per pure-Neumann component) */
+} fvem_op;
+
+fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x_dev, double *y_dev,
+                       void *hip_stream);
+
+/* Level data for inspection: copies level l's operator A_l (FP64 CSR as
+ * built on the device) to caller-owned host arrays.  Call first with NULL
+ * arrays to get n_rows and nnz; then row_ptr needs n_rows+1, col/val nnz. */
+fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows, int64_t *nnz,
+                              int64_t *row_ptr, int32_t *col, double *val);
+
+/* Sizes: number of levels, and n_dof / nnz of level l. */
+fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n_dof0,
+                                int64_t *n_vert, int64_t *device_bytes);
+
+void fvem_hierarchy_destroy(fvem_hierarchy *h);
+
+const char *fvem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVEM_H */

@@ -1,0 +1,755 @@
+// C ABI, hierarchy setup and the MG-PCG driver of the FastVEM solver.
+//
+// Solve (paper Sec. 3.1 "solve K p = r", preconditioned per Sec. 4):
+//   b = B u (projected divergence, Sec. 3.2), zero mean on pure-Neumann
+//   components; FP64 flexible PCG (Polak-Ribiere beta, x0 = 0, true-residual
+//   replacement every m iterations, stop on ||b - K x|| / ||b|| <= tol);
+//   preconditioner: one V(1,1) cycle of the Galerkin hierarchy with
+//   degree-5 Chebyshev smoothing of D^-1 A over [lmax/30, lmax], restriction
+//   R = P^T, prolong-and-correct, and a dense semi-definite Cholesky
+//   generalised inverse on the coarsest level.  In the mixed mode the
+//   V-cycle's operators and vectors are FP32 and the coarsest solve FP64.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fvem.h"
+#include "kernels.hpp"
+#include "setup_host.hpp"
+
+namespace fvem {
+
+static thread_local std::string g_last_error;
+
+#define HIPCHECK(call)                                                                              \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) {                                                                         \
+      if (e_ == hipErrorOutOfMemory)                                                                \
+        throw SetupError{FVEM_ERR_OOM, std::string(#call) + ": " + hipGetErrorString(e_)};           \
+      throw SetupError{FVEM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};             \
+    }                                                                                               \
+  } while (0)
+
+struct DevMem {
+  std::vector<void *> ptrs;
+  int64_t bytes = 0;
+  template <typename T>
+  T *alloc(int64_t n) {
+    if (n <= 0) n = 1;
+    void *p = nullptr;
+    HIPCHECK(hipMalloc(&p, sizeof(T) * n));
+    ptrs.push_back(p);
+    bytes += sizeof(T) * n;
+    return static_cast<T *>(p);
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    T *p = alloc<T>(static_cast<int64_t>(v.size()));
+    if (!v.empty()) HIPCHECK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  ~DevMem() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+struct DevCSR {
+  int64_t n = 0, m = 0, nnz = 0;
+  int64_t *rp = nullptr;
+  int32_t *ci = nullptr;
+  double *v64 = nullptr;
+  float *v32 = nullptr;
+  DevCSRView<double> d() const { return {n, m, nnz, rp, ci, v64}; }
+  DevCSRView<float> f() const { return {n, m, nnz, rp, ci, v32}; }
+};
+
+struct Level {
+  int64_t n = 0;
+  DevCSR A, P, R;
+  double *dinv64 = nullptr;
+  float *dinv32 = nullptr;
+  double lmax = 0;
+  std::vector<double> ca, cb;
+  double *b64, *x64, *xb64, *d64, *r64;
+  float *b32, *x32, *xb32, *d32, *r32;
+};
+
+}  // namespace fvem
+
+struct fvem_hierarchy {
+  fvem::DevMem mem;
+  int device = 0;
+  int nlev = 0;
+  std::vector<fvem::Level> lv;
+  fvem::DevCSR B, BT;
+  int64_t nvert = 0, n0 = 0;
+  int32_t *comp0 = nullptr;
+  int ncomp0 = 0;
+  // coarsest level
+  int64_t nc = 0;
+  double *G = nullptr;
+  int32_t *compc = nullptr;
+  int ncompc = 0;
+  double *bc = nullptr, *xc = nullptr;
+  // PCG
+  double *b, *x, *r, *z, *zold, *p, *q, *lam, *partial, *dotout, *mean;
+  double *host = nullptr;  // pinned scalars
+  std::atomic<int> busy{0};
+  // profiling
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  bool profiling = false;
+};
+
+namespace fvem {
+
+static void check(bool ok, const std::string &msg) {
+  if (!ok) throw SetupError{FVEM_ERR_INVALID, msg};
+}
+
+static bool finite_all(const double *v, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+static HostCells cells_of(const fvem_level_desc &L, int64_t n_dof, const char *what) {
+  check(L.n_cells >= 0 && (L.n_cells == 0 || (L.cell_ptr && L.cell_dof)), std::string(what) + ": cell arrays");
+  HostCells c;
+  c.n_cells = L.n_cells;
+  c.ptr.assign(L.cell_ptr, L.cell_ptr + L.n_cells + 1);
+  check(c.ptr[0] == 0, std::string(what) + ": cell_ptr[0] != 0");
+  for (int64_t i = 0; i < L.n_cells; ++i) check(c.ptr[i + 1] >= c.ptr[i], std::string(what) + ": cell_ptr not monotone");
+  c.dof.assign(L.cell_dof, L.cell_dof + c.ptr[L.n_cells]);
+  for (int32_t d : c.dof) check(d >= -1 && d < n_dof, std::string(what) + ": cell DOF index out of range");
+  return c;
+}
+
+static HostCSR csr_of(const fvem_csr &M, int64_t rows, int64_t cols, const char *what) {
+  check(M.n_rows == rows && M.n_cols == cols, std::string(what) + ": shape mismatch");
+  check(M.row_ptr && (M.nnz == 0 || (M.col && M.val)), std::string(what) + ": null arrays");
+  HostCSR A;
+  A.n_rows = rows;
+  A.n_cols = cols;
+  A.rp.assign(M.row_ptr, M.row_ptr + rows + 1);
+  check(A.rp[0] == 0 && A.rp[rows] == M.nnz, std::string(what) + ": row_ptr ends");
+  for (int64_t i = 0; i < rows; ++i) check(A.rp[i + 1] >= A.rp[i], std::string(what) + ": row_ptr not monotone");
+  A.ci.assign(M.col, M.col + M.nnz);
+  A.v.assign(M.val, M.val + M.nnz);
+  for (int32_t j : A.ci) check(j >= 0 && j < cols, std::string(what) + ": column out of range");
+  check(finite_all(A.v.data(), M.nnz), std::string(what) + ": non-finite value");
+  return A;
+}
+
+static DevCSR upload_csr(fvem_hierarchy *h, const HostCSR &A, bool f32, hipStream_t s) {
+  DevCSR d;
+  d.n = A.n_rows;
+  d.m = A.n_cols;
+  d.nnz = A.nnz();
+  d.rp = h->mem.upload(A.rp, s);
+  d.ci = h->mem.upload(A.ci, s);
+  d.v64 = h->mem.upload(A.v, s);
+  if (f32) {
+    d.v32 = h->mem.alloc<float>(d.nnz);
+    cast_f64_f32(d.nnz, d.v64, d.v32, s);
+  }
+  return d;
+}
+
+static void cheb_coefficients(Level &L, int deg, double lower) {
+  const double hi = L.lmax, lo = lower * L.lmax;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  L.ca.assign(deg, 0.0);
+  L.cb.assign(deg, 0.0);
+  L.cb[0] = 1.0 / theta;
+  for (int j = 1; j < deg; ++j) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    L.ca[j] = rn * rho;
+    L.cb[j] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options *o, hipStream_t s) {
+  check(g != nullptr, "null descriptor");
+  check(g->n_levels >= 1 && g->levels, "n_levels < 1");
+  const int L = g->n_levels;
+  const int deg = (o && o->cheb_degree > 0) ? o->cheb_degree : 5;
+  const double lower = (o && o->cheb_lower > 0) ? o->cheb_lower : 1.0 / 30.0;
+  const int64_t dense_max = (o && o->coarse_dense_max > 0) ? o->coarse_dense_max : 16384;
+  const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 1e-10;
+  HIPCHECK(hipGetDevice(&h->device));
+  h->nlev = L;
+  h->lv.resize(L);
+  std::vector<HostCells> cells(L);
+  for (int l = 0; l < L; ++l) {
+    check(g->levels[l].n_dof >= 0 && g->levels[l].n_dof < (int64_t(1) << 31), "n_dof out of range");
+    cells[l] = cells_of(g->levels[l], g->levels[l].n_dof, "level cells");
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    check(g->levels[l].parent != nullptr, "parent map missing");
+    for (int64_t c = 0; c < cells[l].n_cells; ++c)
+      check(g->levels[l].parent[c] >= 0 && g->levels[l].parent[c] < cells[l + 1].n_cells, "parent out of range");
+  }
+  // level-0 element stiffness blocks
+  const HostCells &c0 = cells[0];
+  HostBlocks ke;
+  check(g->ke_ptr && g->ke_val, "element stiffness missing");
+  ke.off.assign(g->ke_ptr, g->ke_ptr + c0.n_cells + 1);
+  for (int64_t c = 0; c < c0.n_cells; ++c) {
+    const int64_t m = c0.ptr[c + 1] - c0.ptr[c];
+    check(ke.off[c + 1] - ke.off[c] == m * m, "element stiffness block size");
+  }
+  ke.val.assign(g->ke_val, g->ke_val + ke.off[c0.n_cells]);
+  check(finite_all(ke.val.data(), ke.off[c0.n_cells]), "element stiffness: non-finite value");
+  h->n0 = g->levels[0].n_dof;
+  // divergence
+  h->nvert = g->n_vert;
+  check(g->n_vert >= 0, "n_vert");
+  HostCSR Bh;
+  if (g->n_vert > 0) {
+    check(g->cell_vptr && g->cell_vert && g->be_ptr && g->be_val, "divergence blocks missing");
+    HostCells vc;
+    vc.n_cells = c0.n_cells;
+    vc.ptr.resize(c0.n_cells + 1);
+    vc.ptr[0] = 0;
+    std::vector<int32_t> vdof;
+    for (int64_t c = 0; c < c0.n_cells; ++c) {
+      for (int64_t k = g->cell_vptr[c]; k < g->cell_vptr[c + 1]; ++k) {
+        const int32_t v = g->cell_vert[k];
+        check(v >= 0 && v < g->n_vert, "cell vertex out of range");
+        for (int d = 0; d < 3; ++d) vdof.push_back(3 * v + d);
+      }
+      vc.ptr[c + 1] = static_cast<int64_t>(vdof.size());
+    }
+    vc.dof = std::move(vdof);
+    HostBlocks be;
+    be.off.assign(g->be_ptr, g->be_ptr + c0.n_cells + 1);
+    for (int64_t c = 0; c < c0.n_cells; ++c)
+      check(be.off[c + 1] - be.off[c] == (c0.ptr[c + 1] - c0.ptr[c]) * (vc.ptr[c + 1] - vc.ptr[c]),
+            "divergence block size");
+    be.val.assign(g->be_val, g->be_val + be.off[c0.n_cells]);
+    check(finite_all(be.val.data(), be.off[c0.n_cells]), "divergence: non-finite value");
+    Bh = assemble_blocks(h->n0, 3 * g->n_vert, c0, vc, be);
+  }
+  // components of level 0
+  std::vector<int32_t> comp0(h->n0, -1);
+  if (g->component) comp0.assign(g->component, g->component + h->n0);
+  h->ncomp0 = g->n_components;
+  for (int32_t c : comp0) check(c >= -1 && c < h->ncomp0, "component id out of range");
+
+  // operators per level: A_0 from element blocks, A_{l+1} element-wise Galerkin
+  std::vector<HostCSR> A(L), P(L);
+  A[0] = assemble_blocks(h->n0, h->n0, c0, c0, ke);
+  HostBlocks kcur = std::move(ke);
+  for (int l = 0; l + 1 < L; ++l) {
+    const int64_t nf = g->levels[l].n_dof, nc = g->levels[l + 1].n_dof;
+    P[l] = csr_of(g->levels[l].P, nf, nc, "prolongation");
+    HostBlocks knext = galerkin_blocks(cells[l], kcur, g->levels[l].parent, cells[l + 1], P[l]);
+    A[l + 1] = assemble_blocks(nc, nc, cells[l + 1], cells[l + 1], knext);
+    kcur = std::move(knext);
+  }
+  { HostBlocks().val.swap(kcur.val); }
+
+  // upload
+  for (int l = 0; l < L; ++l) {
+    Level &V = h->lv[l];
+    V.n = A[l].n_rows;
+    V.A = upload_csr(h, A[l], true, s);
+    std::vector<double> dinv(V.n);
+    for (int64_t i = 0; i < V.n; ++i) {
+      double d = 0.0;
+      for (int64_t k = A[l].rp[i]; k < A[l].rp[i + 1]; ++k)
+        if (A[l].ci[k] == i) d = A[l].v[k];
+      dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
+    }
+    V.dinv64 = h->mem.upload(dinv, s);
+    V.dinv32 = h->mem.alloc<float>(V.n);
+    cast_f64_f32(V.n, V.dinv64, V.dinv32, s);
+    V.lmax = gershgorin_scaled(A[l]);
+    cheb_coefficients(V, deg, lower);
+    if (l + 1 < L) {
+      V.P = upload_csr(h, P[l], true, s);
+      V.R = upload_csr(h, transpose(P[l]), true, s);
+    }
+    V.b64 = h->mem.alloc<double>(V.n);
+    V.x64 = h->mem.alloc<double>(V.n);
+    V.xb64 = h->mem.alloc<double>(V.n);
+    V.d64 = h->mem.alloc<double>(V.n);
+    V.r64 = h->mem.alloc<double>(V.n);
+    V.b32 = h->mem.alloc<float>(V.n);
+    V.x32 = h->mem.alloc<float>(V.n);
+    V.xb32 = h->mem.alloc<float>(V.n);
+    V.d32 = h->mem.alloc<float>(V.n);
+    V.r32 = h->mem.alloc<float>(V.n);
+  }
+  if (g->n_vert > 0) {
+    h->B = upload_csr(h, Bh, false, s);
+    h->BT = upload_csr(h, transpose(Bh), false, s);
+  }
+  h->comp0 = h->mem.upload(comp0, s);
+
+  // coarsest level: dense semi-definite factorisation and generalised inverse
+  const HostCSR &Ac = A[L - 1];
+  h->nc = Ac.n_rows;
+  check(h->nc <= dense_max, "coarsest level exceeds coarse_dense_max");
+  {
+    int32_t ncc = 0;
+    std::vector<int32_t> cc = floating_components(Ac, &ncc);
+    h->compc = h->mem.upload(cc, s);
+    h->ncompc = ncc;
+    const int64_t n = h->nc;
+    std::vector<double> diag0(n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = Ac.rp[i]; k < Ac.rp[i + 1]; ++k)
+        if (Ac.ci[k] == i) diag0[i] = Ac.v[k];
+    double *dg = h->mem.upload(diag0, s);
+    DevMem tmp;
+    double *D = tmp.alloc<double>(n * n);
+    double *X = tmp.alloc<double>(n * n);
+    int *flag = tmp.alloc<int>(1);
+    HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), s));
+    const Level &C = h->lv[L - 1];
+    dense_from_csr(n, C.A.rp, C.A.ci, C.A.v64, D, s);
+    potrf_semidefinite(D, n, dg, rcond, flag, s);
+    trinv_semidefinite(D, X, n, s);
+    h->G = h->mem.alloc<double>(n * n);
+    // G = X^T X
+    gemm_f64(n, n, n, 1.0, X, n, 1, X, 1, n, 0.0, h->G, n, false, s);
+    int hflag = 0;
+    HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (hflag) throw SetupError{FVEM_ERR_NOT_SPD, "coarsest operator has a significantly negative pivot"};
+    h->bc = h->mem.alloc<double>(n);
+    h->xc = h->mem.alloc<double>(n);
+  }
+  // PCG workspace
+  const int64_t n = h->n0;
+  h->b = h->mem.alloc<double>(n);
+  h->x = h->mem.alloc<double>(n);
+  h->r = h->mem.alloc<double>(n);
+  h->z = h->mem.alloc<double>(n);
+  h->zold = h->mem.alloc<double>(n);
+  h->p = h->mem.alloc<double>(n);
+  h->q = h->mem.alloc<double>(n);
+  h->partial = h->mem.alloc<double>(2 * MAX_COMP * REDUCE_BLOCKS);
+  h->dotout = h->mem.alloc<double>(8);
+  h->mean = h->mem.alloc<double>(MAX_COMP);
+  h->lam = h->mem.alloc<double>(n);
+  HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&h->host), 8 * sizeof(double), hipHostMallocDefault));
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- V-cycle
+
+template <typename T> struct Vec;
+template <> struct Vec<double> {
+  static double *b(Level &L) { return L.b64; }
+  static double *&x(Level &L) { return L.x64; }
+  static double *&xb(Level &L) { return L.xb64; }
+  static double *d(Level &L) { return L.d64; }
+  static double *r(Level &L) { return L.r64; }
+  static const double *dinv(Level &L) { return L.dinv64; }
+  static DevCSRView<double> A(Level &L) { return L.A.d(); }
+  static DevCSRView<double> P(Level &L) { return L.P.d(); }
+  static DevCSRView<double> R(Level &L) { return L.R.d(); }
+};
+template <> struct Vec<float> {
+  static float *b(Level &L) { return L.b32; }
+  static float *&x(Level &L) { return L.x32; }
+  static float *&xb(Level &L) { return L.xb32; }
+  static float *d(Level &L) { return L.d32; }
+  static float *r(Level &L) { return L.r32; }
+  static const float *dinv(Level &L) { return L.dinv32; }
+  static DevCSRView<float> A(Level &L) { return L.A.f(); }
+  static DevCSRView<float> P(Level &L) { return L.P.f(); }
+  static DevCSRView<float> R(Level &L) { return L.R.f(); }
+};
+
+static void ev_record(fvem_hierarchy *h, hipStream_t s) {
+  if (h->ev_used == h->ev.size()) {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    h->ev.push_back(e);
+  }
+  HIPCHECK(hipEventRecord(h->ev[h->ev_used++], s));
+}
+
+template <typename T>
+static void coarse_solve(fvem_hierarchy *h, hipStream_t s) {
+  Level &C = h->lv[h->nlev - 1];
+  const int64_t n = h->nc;
+  if constexpr (sizeof(T) == 4) {
+    cast_scale(n, C.b32, h->bc, 1.0, s);
+  } else {
+    HIPCHECK(hipMemcpyAsync(h->bc, C.b64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
+  if (h->ncompc) project_components(n, h->bc, h->compc, h->ncompc, h->partial, h->mean, s);
+  symv(n, h->G, h->bc, h->xc, s);
+  if (h->ncompc) project_components(n, h->xc, h->compc, h->ncompc, h->partial, h->mean, s);
+  if constexpr (sizeof(T) == 4) {
+    cast_scale(n, h->xc, C.x32, 1.0, s);
+  } else {
+    HIPCHECK(hipMemcpyAsync(C.x64, h->xc, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+template <typename T>
+static void smooth(fvem_hierarchy *h, int l, bool from_zero, hipStream_t s) {
+  Level &L = h->lv[l];
+  using V = Vec<T>;
+  const int deg = static_cast<int>(L.ca.size());
+  int j0 = 0;
+  if (from_zero) {
+    cheb_first<T>(L.n, V::b(L), V::dinv(L), V::d(L), V::x(L), static_cast<T>(L.cb[0]), s);
+    j0 = 1;
+  }
+  for (int j = j0; j < deg; ++j) {
+    const bool prof = h->profiling && l == 0;
+    if (prof) ev_record(h, s);
+    cheb_step<T>(V::A(L), V::b(L), V::dinv(L), V::x(L), V::d(L), V::xb(L), static_cast<T>(L.ca[j]),
+                 static_cast<T>(L.cb[j]), s);
+    if (prof) ev_record(h, s);
+    std::swap(V::x(L), V::xb(L));
+  }
+}
+
+template <typename T>
+static void vcycle(fvem_hierarchy *h, int l, hipStream_t s) {
+  if (l == h->nlev - 1) {
+    coarse_solve<T>(h, s);
+    return;
+  }
+  using V = Vec<T>;
+  Level &L = h->lv[l];
+  Level &N = h->lv[l + 1];
+  smooth<T>(h, l, true, s);
+  residual<T>(V::A(L), V::x(L), V::b(L), V::r(L), s);
+  spmv<T>(V::R(L), V::r(L), V::b(N), s);
+  vcycle<T>(h, l + 1, s);
+  spmv_add<T>(V::P(L), V::x(N), V::x(L), s);
+  smooth<T>(h, l, false, s);
+}
+
+// z = M r (level-0 input r, FP64), projected
+static void precondition(fvem_hierarchy *h, const double *r, double *z, bool mixed, double rnorm, hipStream_t s) {
+  Level &L0 = h->lv[0];
+  const int64_t n = h->n0;
+  if (h->nlev == 1) {
+    HIPCHECK(hipMemcpyAsync(h->bc, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (h->ncompc) project_components(n, h->bc, h->compc, h->ncompc, h->partial, h->mean, s);
+    symv(n, h->G, h->bc, z, s);
+  } else if (mixed) {
+    const double sc = rnorm > 0 ? 1.0 / rnorm : 1.0;
+    cast_scale(n, r, L0.b32, sc, s);
+    vcycle<float>(h, 0, s);
+    cast_scale(n, L0.x32, z, 1.0 / sc, s);
+  } else {
+    HIPCHECK(hipMemcpyAsync(L0.b64, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    vcycle<double>(h, 0, s);
+    HIPCHECK(hipMemcpyAsync(z, L0.x64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
+  if (h->ncomp0) project_components(n, z, h->comp0, h->ncomp0, h->partial, h->mean, s);
+}
+
+static void dots_host(fvem_hierarchy *h, int nd, const double *a0, const double *b0, const double *a1,
+                      const double *b1, const double *a2, const double *b2, double *out, hipStream_t s) {
+  dots(h->n0, nd, a0, b0, a1, b1, a2, b2, h->partial, h->dotout, s);
+  HIPCHECK(hipMemcpyAsync(h->host, h->dotout, sizeof(double) * nd, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (int j = 0; j < nd; ++j) out[j] = h->host[j];
+}
+
+static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const fvem_solve_opts *so,
+                       fvem_solve_stats *st, hipStream_t s) {
+  const int64_t n = h->n0;
+  const double tol = (so && so->tol > 0) ? so->tol : 1e-8;
+  const int maxit = (so && so->maxit > 0) ? so->maxit : 500;
+  const bool mixed = so && so->precision == FVEM_PREC_MIXED;
+  const int m = (so && so->replace_every > 0) ? so->replace_every : 10;
+  const DevCSRView<double> K = h->lv[0].A.d();
+  HIPCHECK(hipMemcpyAsync(h->b, bin, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (h->ncomp0) project_components(n, h->b, h->comp0, h->ncomp0, h->partial, h->mean, s);
+  double d[3];
+  dots_host(h, 1, h->b, h->b, nullptr, nullptr, nullptr, nullptr, d, s);
+  const double bb = d[0];
+  if (!std::isfinite(bb)) throw SetupError{FVEM_ERR_NONFINITE, "non-finite right-hand side"};
+  fill<double>(n, h->x, 0.0, s);
+  if (bb == 0.0) {
+    HIPCHECK(hipMemcpyAsync(xout, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (st) { st->iterations = 0; st->rel_residual = 0.0; }
+    return FVEM_OK;
+  }
+  const double nb = std::sqrt(bb);
+  HIPCHECK(hipMemcpyAsync(h->r, h->b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  precondition(h, h->r, h->z, mixed, nb, s);
+  HIPCHECK(hipMemcpyAsync(h->p, h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  dots_host(h, 1, h->r, h->z, nullptr, nullptr, nullptr, nullptr, d, s);
+  double rz = d[0];
+  int it = 0;
+  double rel = 1.0;
+  fvem_status status = FVEM_ERR_NOT_CONVERGED;
+  while (it < maxit) {
+    spmv<double>(K, h->p, h->q, s);
+    dots_host(h, 1, h->p, h->q, nullptr, nullptr, nullptr, nullptr, d, s);
+    const double pq = d[0];
+    if (!(pq > 0.0) || !std::isfinite(rz)) throw SetupError{FVEM_ERR_NONFINITE, "CG breakdown (p.Kp <= 0)"};
+    const double alpha = rz / pq;
+    pcg_update_xr(n, alpha, h->p, h->q, h->x, h->r, s);
+    ++it;
+    if (it % m == 0) residual<double>(K, h->x, h->b, h->r, s);
+    dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
+    rel = std::sqrt(d[0]) / nb;
+    if (rel <= tol) {
+      residual<double>(K, h->x, h->b, h->r, s);
+      dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
+      rel = std::sqrt(d[0]) / nb;
+      if (rel <= tol) {
+        status = FVEM_OK;
+        break;
+      }
+    }
+    if (it >= maxit) break;
+    std::swap(h->z, h->zold);
+    precondition(h, h->r, h->z, mixed, std::sqrt(d[0]), s);
+    dots_host(h, 2, h->r, h->z, h->r, h->zold, nullptr, nullptr, d, s);
+    const double beta = (d[0] - d[1]) / rz;
+    rz = d[0];
+    pcg_update_p(n, h->z, beta, h->p, s);
+  }
+  if (status != FVEM_OK) {
+    residual<double>(K, h->x, h->b, h->r, s);
+    dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
+    rel = std::sqrt(d[0]) / nb;
+  }
+  if (h->ncomp0) project_components(n, h->x, h->comp0, h->ncomp0, h->partial, h->mean, s);
+  HIPCHECK(hipMemcpyAsync(xout, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (st) {
+    st->iterations = it;
+    st->rel_residual = rel;
+  }
+  return status;
+}
+
+static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out, const fvem_solve_opts *so,
+                                fvem_solve_stats *st, hipStream_t s, bool adjoint) {
+  const bool velocity = !so || so->input == FVEM_INPUT_VELOCITY;
+  if (velocity && h->nvert == 0) throw SetupError{FVEM_ERR_INVALID, "no divergence operator in this hierarchy"};
+  h->profiling = so && so->profile;
+  h->ev_used = 0;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  HIPCHECK(hipEventRecord(e0, s));
+  fvem_status stt;
+  if (!adjoint) {
+    const double *rhs = in;
+    if (velocity) {
+      spmv<double>(h->B.d(), in, h->q, s);
+      rhs = h->q;
+    }
+    stt = pcg(h, rhs, out, so, st, s);
+  } else {
+    if (velocity) {
+      stt = pcg(h, in, h->lam, so, st, s);
+      spmv<double>(h->BT.d(), h->lam, out, s);
+    } else {
+      stt = pcg(h, in, out, so, st, s);
+    }
+  }
+  HIPCHECK(hipEventRecord(e1, s));
+  HIPCHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    st->ms_total = ms;
+    st->n_levels = h->nlev;
+    st->ms_fine_smoother = 0.0;
+    st->n_fine_smoother = static_cast<int32_t>(h->ev_used / 2);
+    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
+      st->ms_fine_smoother += t;
+    }
+  }
+  h->profiling = false;
+  return stt;
+}
+
+template <typename F>
+static fvem_status guard(F &&f) {
+  try {
+    return f();
+  } catch (const SetupError &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return FVEM_ERR_OOM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return FVEM_ERR_INVALID;
+  }
+}
+
+struct BusyGuard {
+  fvem_hierarchy *h;
+  bool ok;
+  explicit BusyGuard(fvem_hierarchy *hh) : h(hh) {
+    int z = 0;
+    ok = h->busy.compare_exchange_strong(z, 1);
+  }
+  ~BusyGuard() {
+    if (ok) h->busy.store(0);
+  }
+};
+
+}  // namespace fvem
+
+using namespace fvem;
+
+extern "C" {
+
+fvem_status fvem_hierarchy_build(const fvem_grid_desc *g, const fvem_options *o, void *hip_stream,
+                                 fvem_hierarchy **out) {
+  if (!out) {
+    g_last_error = "null output handle";
+    return FVEM_ERR_INVALID;
+  }
+  *out = nullptr;
+  fvem_hierarchy *h = new (std::nothrow) fvem_hierarchy();
+  if (!h) return FVEM_ERR_OOM;
+  fvem_status st = guard([&] {
+    build(h, g, o, static_cast<hipStream_t>(hip_stream));
+    return FVEM_OK;
+  });
+  if (st != FVEM_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return FVEM_OK;
+}
+
+fvem_status fvem_solve(fvem_hierarchy *h, const double *in_dev, double *p_dev, const fvem_solve_opts *so,
+                       fvem_solve_stats *st, void *hip_stream) {
+  if (!h || !in_dev || !p_dev) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  BusyGuard bg(h);
+  if (!bg.ok) {
+    g_last_error = "another solve is running on this handle";
+    return FVEM_ERR_BUSY;
+  }
+  return guard([&] { return solve_common(h, in_dev, p_dev, so, st, static_cast<hipStream_t>(hip_stream), false); });
+}
+
+fvem_status fvem_solve_adjoint(fvem_hierarchy *h, const double *gp_dev, double *gu_dev, const fvem_solve_opts *so,
+                               fvem_solve_stats *st, void *hip_stream) {
+  if (!h || !gp_dev || !gu_dev) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  BusyGuard bg(h);
+  if (!bg.ok) {
+    g_last_error = "another solve is running on this handle";
+    return FVEM_ERR_BUSY;
+  }
+  return guard([&] { return solve_common(h, gp_dev, gu_dev, so, st, static_cast<hipStream_t>(hip_stream), true); });
+}
+
+fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y, void *hip_stream) {
+  if (!h || !x || !y) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  BusyGuard bg(h);
+  if (!bg.ok) {
+    g_last_error = "another call is running on this handle";
+    return FVEM_ERR_BUSY;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  return guard([&] {
+    const int64_t n = h->n0;
+    switch (op) {
+      case FVEM_OP_K: spmv<double>(h->lv[0].A.d(), x, y, s); break;
+      case FVEM_OP_B:
+        check(h->nvert > 0, "no divergence operator");
+        spmv<double>(h->B.d(), x, y, s);
+        break;
+      case FVEM_OP_BT:
+        check(h->nvert > 0, "no divergence operator");
+        spmv<double>(h->BT.d(), x, y, s);
+        break;
+      case FVEM_OP_VCYCLE:
+      case FVEM_OP_VCYCLE32: {
+        HIPCHECK(hipMemcpyAsync(h->r, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        double nr = 1.0;
+        if (op == FVEM_OP_VCYCLE32) {
+          double d[1];
+          dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
+          nr = std::sqrt(d[0]);
+        }
+        precondition(h, h->r, y, op == FVEM_OP_VCYCLE32, nr, s);
+        break;
+      }
+      case FVEM_OP_PROJECT:
+        HIPCHECK(hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (h->ncomp0) project_components(n, y, h->comp0, h->ncomp0, h->partial, h->mean, s);
+        break;
+      default: throw SetupError{FVEM_ERR_INVALID, "unknown operator"};
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows, int64_t *nnz, int64_t *row_ptr,
+                              int32_t *col, double *val) {
+  if (!h || level < 0 || level >= h->nlev) {
+    g_last_error = "bad handle or level";
+    return FVEM_ERR_INVALID;
+  }
+  return guard([&] {
+    const DevCSR &A = h->lv[level].A;
+    if (n_rows) *n_rows = A.n;
+    if (nnz) *nnz = A.nnz;
+    if (row_ptr) HIPCHECK(hipMemcpy(row_ptr, A.rp, sizeof(int64_t) * (A.n + 1), hipMemcpyDeviceToHost));
+    if (col) HIPCHECK(hipMemcpy(col, A.ci, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost));
+    if (val) HIPCHECK(hipMemcpy(val, A.v64, sizeof(double) * A.nnz, hipMemcpyDeviceToHost));
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n_dof0, int64_t *n_vert,
+                                int64_t *device_bytes) {
+  if (!h) {
+    g_last_error = "null handle";
+    return FVEM_ERR_INVALID;
+  }
+  if (n_levels) *n_levels = h->nlev;
+  if (n_dof0) *n_dof0 = h->n0;
+  if (n_vert) *n_vert = h->nvert;
+  if (device_bytes) *device_bytes = h->mem.bytes;
+  return FVEM_OK;
+}
+
+void fvem_hierarchy_destroy(fvem_hierarchy *h) {
+  if (!h) return;
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->host) (void)hipHostFree(h->host);
+  delete h;
+}
+
+const char *fvem_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

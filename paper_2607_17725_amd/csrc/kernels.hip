@@ -1,0 +1,543 @@
+// HIP kernels for the FastVEM MG-PCG solve on CDNA4 (gfx950).
+//
+// Every hot kernel is HBM-bandwidth bound (SpMV-shaped, ~0.2 flop/byte);
+// the only dense contraction is the coarsest-level factorisation, which runs
+// on FP64 MFMA.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace fvem {
+
+// ---------------------------------------------------------------- SpMV family
+//
+// Vector-CSR: a group of G lanes owns one row; lanes stride over the row's
+// entries (coalesced value/index loads), reduce with cross-lane shuffles and
+// lane 0 applies the epilogue.  All variants read A, the gathered x and the
+// per-row vectors exactly once.
+
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+template <int G, typename VT, typename XT, class Epi>
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t n, const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const VT *__restrict__ val, const XT *__restrict__ x,
+                                                   Epi epi) {
+  const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  using AT = typename Epi::acc_t;
+  AT acc = 0;
+  const int64_t e = rp[row + 1];
+  for (int64_t k = rp[row] + lane; k < e; k += G) acc += static_cast<AT>(val[k]) * static_cast<AT>(x[ci[k]]);
+  acc = group_sum<G, AT>(acc);
+  if (lane == 0) epi(row, acc);
+}
+
+template <typename T>
+struct EpiStore {
+  using acc_t = T;
+  T *y;
+  __device__ void operator()(int64_t i, T a) const { y[i] = a; }
+};
+
+template <typename T>
+struct EpiResidual {  // y = b - A x
+  using acc_t = T;
+  const T *b;
+  T *y;
+  __device__ void operator()(int64_t i, T a) const { y[i] = b[i] - a; }
+};
+
+template <typename T>
+struct EpiAdd {  // y += A x  (prolong-and-correct)
+  using acc_t = T;
+  T *y;
+  __device__ void operator()(int64_t i, T a) const { y[i] += a; }
+};
+
+template <typename T>
+struct EpiCheb {  // d = ca d + cb dinv (b - A xin);  xout = xin + d
+  using acc_t = T;
+  const T *b, *dinv, *xin;
+  T *d, *xout;
+  T ca, cb;
+  __device__ void operator()(int64_t i, T a) const {
+    const T dn = ca * d[i] + cb * dinv[i] * (b[i] - a);
+    d[i] = dn;
+    xout[i] = xin[i] + dn;
+  }
+};
+
+static int group_for(int64_t n, int64_t nnz) {
+  const double avg = n > 0 ? static_cast<double>(nnz) / n : 1.0;
+  if (avg > 96) return 64;
+  if (avg > 40) return 32;
+  if (avg > 12) return 16;
+  return 8;
+}
+
+template <typename VT, typename XT, class Epi>
+static void launch_spmv(const DevCSRView<VT> &A, const XT *x, Epi epi, hipStream_t s) {
+  if (A.n == 0) return;
+  const int G = group_for(A.n, A.nnz);
+  const int64_t rows_per_block = 256 / G;
+  const dim3 grid(static_cast<unsigned>((A.n + rows_per_block - 1) / rows_per_block));
+  switch (G) {
+    case 64: spmv_kernel<64, VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, A.v, x, epi); break;
+    case 32: spmv_kernel<32, VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, A.v, x, epi); break;
+    case 16: spmv_kernel<16, VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, A.v, x, epi); break;
+    default: spmv_kernel<8, VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, A.v, x, epi); break;
+  }
+}
+
+template <typename T>
+void spmv(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s) {
+  launch_spmv(A, x, EpiStore<T>{y}, s);
+}
+template <typename T>
+void residual(const DevCSRView<T> &A, const T *x, const T *b, T *r, hipStream_t s) {
+  launch_spmv(A, x, EpiResidual<T>{b, r}, s);
+}
+template <typename T>
+void spmv_add(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s) {
+  launch_spmv(A, x, EpiAdd<T>{y}, s);
+}
+template <typename T>
+void cheb_step(const DevCSRView<T> &A, const T *b, const T *dinv, const T *xin, T *d, T *xout, T ca, T cb,
+               hipStream_t s) {
+  launch_spmv(A, xin, EpiCheb<T>{b, dinv, xin, d, xout, ca, cb}, s);
+}
+
+template void spmv<double>(const DevCSRView<double> &, const double *, double *, hipStream_t);
+template void spmv<float>(const DevCSRView<float> &, const float *, float *, hipStream_t);
+template void residual<double>(const DevCSRView<double> &, const double *, const double *, double *,
+                               hipStream_t);
+template void residual<float>(const DevCSRView<float> &, const float *, const float *, float *, hipStream_t);
+template void spmv_add<double>(const DevCSRView<double> &, const double *, double *, hipStream_t);
+template void spmv_add<float>(const DevCSRView<float> &, const float *, float *, hipStream_t);
+template void cheb_step<double>(const DevCSRView<double> &, const double *, const double *, const double *,
+                                double *, double *, double, double, hipStream_t);
+template void cheb_step<float>(const DevCSRView<float> &, const float *, const float *, const float *,
+                               float *, float *, float, float, hipStream_t);
+
+// ---------------------------------------------------------------- vectors
+
+template <typename T>
+__global__ void cheb_first_kernel(int64_t n, const T *b, const T *dinv, T *d, T *x, T cb) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const T v = cb * dinv[i] * b[i];
+    d[i] = v;
+    x[i] = v;
+  }
+}
+
+static dim3 vgrid(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return dim3(static_cast<unsigned>(b));
+}
+
+template <typename T>
+void cheb_first(int64_t n, const T *b, const T *dinv, T *d, T *x, T cb, hipStream_t s) {
+  if (n) cheb_first_kernel<<<vgrid(n), 256, 0, s>>>(n, b, dinv, d, x, cb);
+}
+template void cheb_first<double>(int64_t, const double *, const double *, double *, double *, double,
+                                 hipStream_t);
+template void cheb_first<float>(int64_t, const float *, const float *, float *, float *, float, hipStream_t);
+
+__global__ void cast_scale_kernel_df(int64_t n, const double *a, float *b, double s) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b[i] = static_cast<float>(a[i] * s);
+}
+__global__ void cast_scale_kernel_fd(int64_t n, const float *a, double *b, double s) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b[i] = static_cast<double>(a[i]) * s;
+}
+void cast_scale(int64_t n, const double *a, float *b, double s, hipStream_t st) {
+  if (n) cast_scale_kernel_df<<<vgrid(n), 256, 0, st>>>(n, a, b, s);
+}
+void cast_scale(int64_t n, const float *a, double *b, double s, hipStream_t st) {
+  if (n) cast_scale_kernel_fd<<<vgrid(n), 256, 0, st>>>(n, a, b, s);
+}
+
+__global__ void axpy2_kernel(int64_t n, double alpha, const double *p, const double *q, double *x, double *r) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+void pcg_update_xr(int64_t n, double alpha, const double *p, const double *q, double *x, double *r,
+                   hipStream_t s) {
+  if (n) axpy2_kernel<<<vgrid(n), 256, 0, s>>>(n, alpha, p, q, x, r);
+}
+
+__global__ void xpby_kernel(int64_t n, const double *z, double beta, double *p) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+void pcg_update_p(int64_t n, const double *z, double beta, double *p, hipStream_t s) {
+  if (n) xpby_kernel<<<vgrid(n), 256, 0, s>>>(n, z, beta, p);
+}
+
+template <typename T>
+__global__ void fill_kernel(int64_t n, T *a, T v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+template <typename T>
+void fill(int64_t n, T *a, T v, hipStream_t s) {
+  if (n) fill_kernel<<<vgrid(n), 256, 0, s>>>(n, a, v);
+}
+template void fill<double>(int64_t, double *, double, hipStream_t);
+template void fill<float>(int64_t, float *, float, hipStream_t);
+
+// ---------------------------------------------------------------- reductions
+//
+// Deterministic: a fixed grid of REDUCE_BLOCKS blocks accumulates strided
+// partial sums; one block adds the partials in a fixed order.  Up to four
+// dot products share one pass over the vectors.
+
+template <int NDOT>
+__global__ __launch_bounds__(256) void dots_partial_kernel(int64_t n, const double *a0, const double *b0,
+                                                           const double *a1, const double *b1,
+                                                           const double *a2, const double *b2,
+                                                           double *partial) {
+  double acc[NDOT];
+#pragma unroll
+  for (int j = 0; j < NDOT; ++j) acc[j] = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    acc[0] += a0[i] * b0[i];
+    if (NDOT > 1) acc[1] += a1[i] * b1[i];
+    if (NDOT > 2) acc[2] += a2[i] * b2[i];
+  }
+  __shared__ double sh[NDOT][4];
+#pragma unroll
+  for (int j = 0; j < NDOT; ++j) {
+    double v = acc[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[j][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NDOT) {
+    const int j = threadIdx.x;
+    partial[j * REDUCE_BLOCKS + blockIdx.x] = ((sh[j][0] + sh[j][1]) + (sh[j][2] + sh[j][3]));
+  }
+}
+
+template <int NDOT>
+__global__ __launch_bounds__(256) void dots_final_kernel(const double *partial, double *out) {
+  __shared__ double sh[256];
+  for (int j = 0; j < NDOT; ++j) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < REDUCE_BLOCKS; i += 256) v += partial[j * REDUCE_BLOCKS + i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = sh[0];
+    __syncthreads();
+  }
+}
+
+void dots(int64_t n, int ndot, const double *a0, const double *b0, const double *a1, const double *b1,
+          const double *a2, const double *b2, double *partial, double *out, hipStream_t s) {
+  const dim3 g(REDUCE_BLOCKS);
+  switch (ndot) {
+    case 1:
+      dots_partial_kernel<1><<<g, 256, 0, s>>>(n, a0, b0, a1, b1, a2, b2, partial);
+      dots_final_kernel<1><<<1, 256, 0, s>>>(partial, out);
+      break;
+    case 2:
+      dots_partial_kernel<2><<<g, 256, 0, s>>>(n, a0, b0, a1, b1, a2, b2, partial);
+      dots_final_kernel<2><<<1, 256, 0, s>>>(partial, out);
+      break;
+    default:
+      dots_partial_kernel<3><<<g, 256, 0, s>>>(n, a0, b0, a1, b1, a2, b2, partial);
+      dots_final_kernel<3><<<1, 256, 0, s>>>(partial, out);
+      break;
+  }
+}
+
+// Zero mean per pure-Neumann component (up to MAX_COMP components per pass).
+__global__ __launch_bounds__(256) void comp_partial_kernel(int64_t n, const double *v, const int32_t *comp,
+                                                           int c0, int nc, double *partial) {
+  __shared__ double s_sum[MAX_COMP];
+  __shared__ double s_cnt[MAX_COMP];
+  for (int j = threadIdx.x; j < nc; j += 256) {
+    s_sum[j] = 0.0;
+    s_cnt[j] = 0.0;
+  }
+  __syncthreads();
+  // sequential per block for determinism: each thread reduces a contiguous chunk
+  const int64_t per_block = (n + REDUCE_BLOCKS - 1) / REDUCE_BLOCKS;
+  const int64_t lo = blockIdx.x * per_block;
+  const int64_t hi = lo + per_block < n ? lo + per_block : n;
+  if (threadIdx.x == 0) {
+    for (int64_t i = lo; i < hi; ++i) {
+      const int c = comp[i] - c0;
+      if (c >= 0 && c < nc) {
+        s_sum[c] += v[i];
+        s_cnt[c] += 1.0;
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nc; j += 256) {
+    partial[(2 * j) * REDUCE_BLOCKS + blockIdx.x] = s_sum[j];
+    partial[(2 * j + 1) * REDUCE_BLOCKS + blockIdx.x] = s_cnt[j];
+  }
+}
+
+__global__ void comp_final_kernel(int nc, const double *partial, double *mean) {
+  const int j = blockIdx.x;
+  __shared__ double sh[2][256];
+  double s = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < REDUCE_BLOCKS; i += 256) {
+    s += partial[(2 * j) * REDUCE_BLOCKS + i];
+    c += partial[(2 * j + 1) * REDUCE_BLOCKS + i];
+  }
+  sh[0][threadIdx.x] = s;
+  sh[1][threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mean[j] = sh[1][0] > 0 ? sh[0][0] / sh[1][0] : 0.0;
+}
+
+__global__ void comp_sub_kernel(int64_t n, double *v, const int32_t *comp, int c0, int nc, const double *mean) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int c = comp[i] - c0;
+    if (c >= 0 && c < nc) v[i] -= mean[c];
+  }
+}
+
+void project_components(int64_t n, double *v, const int32_t *comp, int n_comp, double *partial, double *mean,
+                        hipStream_t s) {
+  for (int c0 = 0; c0 < n_comp; c0 += MAX_COMP) {
+    const int nc = n_comp - c0 < MAX_COMP ? n_comp - c0 : MAX_COMP;
+    comp_partial_kernel<<<REDUCE_BLOCKS, 256, 0, s>>>(n, v, comp, c0, nc, partial);
+    comp_final_kernel<<<nc, 256, 0, s>>>(nc, partial, mean);
+    comp_sub_kernel<<<vgrid(n), 256, 0, s>>>(n, v, comp, c0, nc, mean);
+  }
+}
+
+// ---------------------------------------------------------------- dense FP64 (coarsest level)
+//
+// Symmetric positive semi-definite factorisation A = L L^T, right-looking in
+// column blocks of NB: factor the diagonal block in LDS (a pivot below
+// rcond * a_jj of the original matrix zeroes its column), solve the panel
+// below it, update the trailing matrix with an FP64 MFMA GEMM.  Matrices are
+// column-major with leading dimension ld.
+
+constexpr int NB = 64;
+
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double *A, int64_t ld, int64_t k0, int nb,
+                                                         const double *diag0, double rcond, int *flag) {
+  __shared__ double L[NB][NB + 1];
+  for (int t = threadIdx.x; t < nb * nb; t += 256) {
+    const int i = t % nb, j = t / nb;
+    L[i][j] = A[(k0 + i) + (k0 + j) * ld];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = L[j][j];
+    const double thr = rcond * diag0[k0 + j];
+    __syncthreads();
+    const bool zero = !(d > thr);
+    if (threadIdx.x == 0 && d < -1e-6 * diag0[k0 + j]) atomicOr(flag, 1);
+    const double piv = zero ? 0.0 : sqrt(d);
+    if (threadIdx.x == 0) L[j][j] = piv;
+    for (int i = j + 1 + threadIdx.x; i < nb; i += 256) L[i][j] = zero ? 0.0 : L[i][j] / piv;
+    __syncthreads();
+    // trailing update inside the block (lower triangle)
+    for (int t = threadIdx.x; t < nb * nb; t += 256) {
+      const int i = t % nb, c = t / nb;
+      if (c > j && i >= c) L[i][c] -= L[i][j] * L[c][j];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nb * nb; t += 256) {
+    const int i = t % nb, j = t / nb;
+    A[(k0 + i) + (k0 + j) * ld] = (i >= j) ? L[i][j] : 0.0;
+  }
+}
+
+// Rows below the diagonal block: L21 = A21 L11^-T (row-parallel forward substitution).
+__global__ __launch_bounds__(256) void trsm_panel_kernel(double *A, int64_t ld, int64_t n, int64_t k0, int nb) {
+  __shared__ double L[NB][NB + 1];
+  for (int t = threadIdx.x; t < nb * nb; t += 256) {
+    const int i = t % nb, j = t / nb;
+    L[i][j] = A[(k0 + i) + (k0 + j) * ld];
+  }
+  __syncthreads();
+  const int64_t row = k0 + nb + blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (row >= n) return;
+  double x[NB];
+  for (int j = 0; j < nb; ++j) {
+    double s = A[row + (k0 + j) * ld];
+    for (int t = 0; t < j; ++t) s -= x[t] * L[j][t];
+    x[j] = (L[j][j] != 0.0) ? s / L[j][j] : 0.0;
+  }
+  for (int j = 0; j < nb; ++j) A[row + (k0 + j) * ld] = x[j];
+}
+
+// C[m0.., n0..] (+)= alpha * op(A) op(B), MFMA f64 16x16x4.  op(A)(i,k) =
+// A[i*sai + k*sak], op(B)(k,j) = B[k*sbk + j*sbj], C column-major (ldc).
+// One wave computes a 16x16 tile; a block of 4 waves covers 32x32.
+// Only tiles with tile_row >= tile_col are computed when lower_only is set.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                       const double *A, int64_t sai, int64_t sak,
+                                                       const double *B, int64_t sbk, int64_t sbj, double beta,
+                                                       double *C, int64_t ldc, int lower_only) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t i0 = (static_cast<int64_t>(blockIdx.x) * 2 + (wave & 1)) * 16;
+  const int64_t j0 = (static_cast<int64_t>(blockIdx.y) * 2 + (wave >> 1)) * 16;
+  if (i0 >= M || j0 >= N) return;
+  if (lower_only && i0 + 15 < j0) return;
+  const int r = lane & 15;   // row of A / column of B
+  const int kk = lane >> 4;  // k within the 4-step
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  const int64_t ia = i0 + r, jb = j0 + r;
+  for (int64_t k = 0; k < K; k += 4) {
+    const int64_t kc = k + kk;
+    const double a = (ia < M && kc < K) ? A[ia * sai + kc * sak] : 0.0;
+    const double b = (jb < N && kc < K) ? B[kc * sbk + jb * sbj] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  // D layout: lane holds rows 4*(lane/16) + q, column lane%16
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = i0 + 4 * (lane >> 4) + q;
+    const int64_t j = j0 + (lane & 15);
+    if (i < M && j < N) {
+      double *c = C + i + j * ldc;
+      *c = alpha * acc[q] + (beta == 0.0 ? 0.0 : beta * *c);
+    }
+  }
+}
+
+void gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t sai, int64_t sak,
+              const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc, bool lower_only,
+              hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  const dim3 g(static_cast<unsigned>((M + 31) / 32), static_cast<unsigned>((N + 31) / 32));
+  gemm_f64_kernel<<<g, 256, 0, s>>>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc, lower_only ? 1 : 0);
+}
+
+void potrf_semidefinite(double *A, int64_t n, const double *diag0, double rcond, int *flag, hipStream_t s) {
+  for (int64_t k0 = 0; k0 < n; k0 += NB) {
+    const int nb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
+    potrf_diag_kernel<<<1, 256, 0, s>>>(A, n, k0, nb, diag0, rcond, flag);
+    const int64_t rest = n - k0 - nb;
+    if (rest <= 0) break;
+    trsm_panel_kernel<<<static_cast<unsigned>((rest + 255) / 256), 256, 0, s>>>(A, n, n, k0, nb);
+    // A22 -= L21 L21^T (lower triangle)
+    const double *L21 = A + (k0 + nb) + k0 * n;
+    double *A22 = A + (k0 + nb) + (k0 + nb) * n;
+    gemm_f64(rest, rest, nb, -1.0, L21, 1, n, L21, n, 1, 1.0, A22, n, true, s);
+  }
+}
+
+// X = L^+ (lower triangular, zero rows for zero pivots): block forward
+// substitution on the identity.  Block row i: T = E_i - L[i,0:i] X[0:i,0:i],
+// then X[i,0:i+1] = L_ii^+ T, column-parallel inside the block.
+__global__ __launch_bounds__(256) void trinv_block_kernel(const double *L, double *X, int64_t n, int64_t i0,
+                                                          int nb) {
+  __shared__ double Lb[NB][NB + 1];
+  for (int t = threadIdx.x; t < nb * nb; t += 256) {
+    const int a = t % nb, b = t / nb;
+    Lb[a][b] = L[(i0 + a) + (i0 + b) * n];
+  }
+  __syncthreads();
+  const int64_t col = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (col >= i0 + nb) return;
+  double x[NB];
+  for (int a = 0; a < nb; ++a) {
+    double s = X[(i0 + a) + col * n];          // holds T (minus the identity)
+    if (col == i0 + a) s += 1.0;
+    for (int t = 0; t < a; ++t) s -= Lb[a][t] * x[t];
+    x[a] = (Lb[a][a] != 0.0) ? s / Lb[a][a] : 0.0;
+  }
+  for (int a = 0; a < nb; ++a) X[(i0 + a) + col * n] = x[a];
+}
+
+void trinv_semidefinite(const double *L, double *X, int64_t n, hipStream_t s) {
+  (void)hipMemsetAsync(X, 0, sizeof(double) * n * n, s);
+  for (int64_t i0 = 0; i0 < n; i0 += NB) {
+    const int nb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
+    if (i0 > 0) {
+      // X[i0:i0+nb, 0:i0] = -L[i0:i0+nb, 0:i0] X[0:i0, 0:i0]
+      gemm_f64(nb, i0, i0, -1.0, L + i0, 1, n, X, 1, n, 0.0, X + i0, n, false, s);
+    }
+    trinv_block_kernel<<<static_cast<unsigned>((i0 + nb + 255) / 256), 256, 0, s>>>(L, X, n, i0, nb);
+  }
+}
+
+// Symmetric dense y = G x (FP64), one wave per row block of 4 rows? keep simple:
+// one 256-thread block per row, coalesced along the row of the column-major
+// symmetric matrix (row i of G = column i).
+__global__ __launch_bounds__(256) void symv_kernel(int64_t n, const double *G, const double *x, double *y) {
+  const int64_t i = blockIdx.x;
+  const double *col = G + i * n;
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) acc += col[k] * x[k];
+  __shared__ double sh[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) y[i] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+void symv(int64_t n, const double *G, const double *x, double *y, hipStream_t s) {
+  if (n) symv_kernel<<<static_cast<unsigned>(n), 256, 0, s>>>(n, G, x, y);
+}
+
+__global__ void dense_from_csr_kernel(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                                      double *D) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) D[i + static_cast<int64_t>(ci[k]) * n] = v[k];
+}
+
+void dense_from_csr(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, double *D, hipStream_t s) {
+  (void)hipMemsetAsync(D, 0, sizeof(double) * n * n, s);
+  if (n) dense_from_csr_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(n, rp, ci, v, D);
+}
+
+__global__ void cast_f64_f32_kernel(int64_t n, const double *a, float *b) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b[i] = static_cast<float>(a[i]);
+}
+void cast_f64_f32(int64_t n, const double *a, float *b, hipStream_t s) {
+  if (n) cast_f64_f32_kernel<<<vgrid(n), 256, 0, s>>>(n, a, b);
+}
+
+}  // namespace fvem

@@ -1,0 +1,55 @@
+// Kernel launchers of the FastVEM solver (implemented in kernels.hip).
+#pragma once
+
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace fvem {
+
+constexpr int REDUCE_BLOCKS = 1024;
+constexpr int MAX_COMP = 64;
+
+template <typename T>
+struct DevCSRView {
+  int64_t n = 0, m = 0, nnz = 0;
+  const int64_t *rp = nullptr;
+  const int32_t *ci = nullptr;
+  const T *v = nullptr;
+};
+
+// SpMV family (vector CSR with fused epilogues)
+template <typename T> void spmv(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s);
+template <typename T> void residual(const DevCSRView<T> &A, const T *x, const T *b, T *r, hipStream_t s);
+template <typename T> void spmv_add(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s);
+template <typename T>
+void cheb_step(const DevCSRView<T> &A, const T *b, const T *dinv, const T *xin, T *d, T *xout, T ca, T cb,
+               hipStream_t s);
+template <typename T> void cheb_first(int64_t n, const T *b, const T *dinv, T *d, T *x, T cb, hipStream_t s);
+
+// vectors
+void cast_scale(int64_t n, const double *a, float *b, double s, hipStream_t st);
+void cast_scale(int64_t n, const float *a, double *b, double s, hipStream_t st);
+void cast_f64_f32(int64_t n, const double *a, float *b, hipStream_t s);
+void pcg_update_xr(int64_t n, double alpha, const double *p, const double *q, double *x, double *r,
+                   hipStream_t s);
+void pcg_update_p(int64_t n, const double *z, double beta, double *p, hipStream_t s);
+template <typename T> void fill(int64_t n, T *a, T v, hipStream_t s);
+
+// deterministic reductions: out[j] = a_j . b_j for j < ndot (ndot <= 3);
+// partial needs 3 * REDUCE_BLOCKS doubles
+void dots(int64_t n, int ndot, const double *a0, const double *b0, const double *a1, const double *b1,
+          const double *a2, const double *b2, double *partial, double *out, hipStream_t s);
+// v -= mean over each pure-Neumann component; partial needs 2 * MAX_COMP * REDUCE_BLOCKS doubles
+void project_components(int64_t n, double *v, const int32_t *comp, int n_comp, double *partial, double *mean,
+                        hipStream_t s);
+
+// dense FP64 (coarsest level), column-major
+void gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t sai, int64_t sak,
+              const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc, bool lower_only,
+              hipStream_t s);
+void potrf_semidefinite(double *A, int64_t n, const double *diag0, double rcond, int *flag, hipStream_t s);
+void trinv_semidefinite(const double *L, double *X, int64_t n, hipStream_t s);
+void symv(int64_t n, const double *G, const double *x, double *y, hipStream_t s);
+void dense_from_csr(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, double *D, hipStream_t s);
+
+}  // namespace fvem

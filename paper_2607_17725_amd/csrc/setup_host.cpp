@@ -1,0 +1,230 @@
+// Host-side hierarchy setup (see setup_host.hpp).
+#include "setup_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <omp.h>
+
+namespace fvem {
+
+namespace {
+
+// DOF -> (cell, local index) incidence, cells in increasing order per DOF.
+void incidence(int64_t n, const HostCells &cells, std::vector<int64_t> &ptr, std::vector<int64_t> &cell,
+               std::vector<int32_t> &loc) {
+  ptr.assign(n + 1, 0);
+  for (int64_t c = 0; c < cells.n_cells; ++c)
+    for (int64_t k = cells.ptr[c]; k < cells.ptr[c + 1]; ++k)
+      if (cells.dof[k] >= 0) ptr[cells.dof[k] + 1]++;
+  for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  cell.resize(ptr[n]);
+  loc.resize(ptr[n]);
+  std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int64_t c = 0; c < cells.n_cells; ++c)
+    for (int64_t k = cells.ptr[c]; k < cells.ptr[c + 1]; ++k) {
+      int32_t d = cells.dof[k];
+      if (d < 0) continue;
+      cell[fill[d]] = c;
+      loc[fill[d]] = static_cast<int32_t>(k - cells.ptr[c]);
+      fill[d]++;
+    }
+}
+
+}  // namespace
+
+HostCSR assemble_blocks(int64_t n_rows, int64_t n_cols, const HostCells &rows, const HostCells &cols,
+                        const HostBlocks &blocks) {
+  std::vector<int64_t> iptr, icell;
+  std::vector<int32_t> iloc;
+  incidence(n_rows, rows, iptr, icell, iloc);
+  HostCSR A;
+  A.n_rows = n_rows;
+  A.n_cols = n_cols;
+  A.rp.assign(n_rows + 1, 0);
+  // symbolic: sorted union of the column lists of the incident cells
+  std::vector<std::vector<int32_t>> pat(n_rows);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n_rows; ++i) {
+    std::vector<int32_t> &p = pat[i];
+    for (int64_t k = iptr[i]; k < iptr[i + 1]; ++k) {
+      int64_t c = icell[k];
+      for (int64_t q = cols.ptr[c]; q < cols.ptr[c + 1]; ++q)
+        if (cols.dof[q] >= 0) p.push_back(cols.dof[q]);
+    }
+    std::sort(p.begin(), p.end());
+    p.erase(std::unique(p.begin(), p.end()), p.end());
+  }
+  for (int64_t i = 0; i < n_rows; ++i) A.rp[i + 1] = A.rp[i] + static_cast<int64_t>(pat[i].size());
+  A.ci.resize(A.rp[n_rows]);
+  A.v.assign(A.rp[n_rows], 0.0);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n_rows; ++i) {
+    const std::vector<int32_t> &p = pat[i];
+    std::copy(p.begin(), p.end(), A.ci.begin() + A.rp[i]);
+    double *row = A.v.data() + A.rp[i];
+    for (int64_t k = iptr[i]; k < iptr[i + 1]; ++k) {
+      int64_t c = icell[k];
+      int32_t a = iloc[k];
+      int64_t m = cols.ptr[c + 1] - cols.ptr[c];
+      const double *blk = blocks.val.data() + blocks.off[c] + static_cast<int64_t>(a) * m;
+      for (int64_t b = 0; b < m; ++b) {
+        int32_t j = cols.dof[cols.ptr[c] + b];
+        if (j < 0) continue;
+        auto it = std::lower_bound(p.begin(), p.end(), j);
+        row[it - p.begin()] += blk[b];
+      }
+    }
+    std::vector<int32_t>().swap(pat[i]);
+  }
+  return A;
+}
+
+HostBlocks galerkin_blocks(const HostCells &fine, const HostBlocks &kf, const int32_t *parent,
+                           const HostCells &coarse, const HostCSR &P) {
+  const int64_t nc = coarse.n_cells;
+  // children of each coarse cell, in increasing fine-cell order
+  std::vector<int64_t> cptr(nc + 1, 0), child(fine.n_cells);
+  for (int64_t f = 0; f < fine.n_cells; ++f) cptr[parent[f] + 1]++;
+  for (int64_t c = 0; c < nc; ++c) cptr[c + 1] += cptr[c];
+  {
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t f = 0; f < fine.n_cells; ++f) child[fill[parent[f]]++] = f;
+  }
+  HostBlocks out;
+  out.off.assign(nc + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t m = coarse.ptr[c + 1] - coarse.ptr[c];
+    out.off[c + 1] = out.off[c] + m * m;
+  }
+  out.val.assign(out.off[nc], 0.0);
+  int bad = 0;
+  int64_t bad_row = -1;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+  for (int64_t E = 0; E < nc; ++E) {
+    const int64_t m = coarse.ptr[E + 1] - coarse.ptr[E];
+    const int32_t *cd = coarse.dof.data() + coarse.ptr[E];
+    double *KE = out.val.data() + out.off[E];
+    std::vector<double> Pf, T;
+    for (int64_t q = cptr[E]; q < cptr[E + 1]; ++q) {
+      const int64_t f = child[q];
+      const int64_t nf = fine.ptr[f + 1] - fine.ptr[f];
+      const int32_t *fd = fine.dof.data() + fine.ptr[f];
+      Pf.assign(nf * m, 0.0);
+      for (int64_t a = 0; a < nf; ++a) {
+        int32_t i = fd[a];
+        if (i < 0) continue;
+        for (int64_t k = P.rp[i]; k < P.rp[i + 1]; ++k) {
+          int32_t J = P.ci[k];
+          int64_t b = 0;
+          while (b < m && cd[b] != J) ++b;
+          if (b == m) {
+            bad = 1;
+#pragma omp critical
+            bad_row = i;
+            continue;
+          }
+          Pf[a * m + b] = P.v[k];
+        }
+      }
+      const double *Kf = kf.val.data() + kf.off[f];
+      // T = K_f P_f  (nf x m), then KE += P_f^T T
+      T.assign(nf * m, 0.0);
+      for (int64_t a = 0; a < nf; ++a)
+        for (int64_t b = 0; b < nf; ++b) {
+          const double kab = Kf[a * nf + b];
+          if (kab == 0.0) continue;
+          const double *pb = &Pf[b * m];
+          double *ta = &T[a * m];
+          for (int64_t j = 0; j < m; ++j) ta[j] += kab * pb[j];
+        }
+      for (int64_t a = 0; a < nf; ++a) {
+        const double *pa = &Pf[a * m];
+        const double *ta = &T[a * m];
+        for (int64_t i = 0; i < m; ++i) {
+          const double w = pa[i];
+          if (w == 0.0) continue;
+          double *ki = KE + i * m;
+          for (int64_t j = 0; j < m; ++j) ki[j] += w * ta[j];
+        }
+      }
+    }
+  }
+  if (bad)
+    throw SetupError{FVEM_ERR_INVALID, "prolongation row " + std::to_string(bad_row) +
+                                           " references a DOF outside the parent cell (not diffusion-free)"};
+  return out;
+}
+
+HostCSR transpose(const HostCSR &A) {
+  HostCSR T;
+  T.n_rows = A.n_cols;
+  T.n_cols = A.n_rows;
+  T.rp.assign(T.n_rows + 1, 0);
+  for (int64_t k = 0; k < A.nnz(); ++k) T.rp[A.ci[k] + 1]++;
+  for (int64_t i = 0; i < T.n_rows; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(A.nnz());
+  T.v.resize(A.nnz());
+  std::vector<int64_t> fill(T.rp.begin(), T.rp.end() - 1);
+  for (int64_t i = 0; i < A.n_rows; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      int64_t dst = fill[A.ci[k]]++;
+      T.ci[dst] = static_cast<int32_t>(i);
+      T.v[dst] = A.v[k];
+    }
+  return T;
+}
+
+double gershgorin_scaled(const HostCSR &A) {
+  double lmax = 0.0;
+#pragma omp parallel for reduction(max : lmax)
+  for (int64_t i = 0; i < A.n_rows; ++i) {
+    double s = 0.0, d = 0.0;
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      s += std::fabs(A.v[k]);
+      if (A.ci[k] == i) d = A.v[k];
+    }
+    if (d > 0.0) lmax = std::max(lmax, s / d);
+  }
+  return lmax;
+}
+
+std::vector<int32_t> floating_components(const HostCSR &A, int32_t *n_comp) {
+  const int64_t n = A.n_rows;
+  std::vector<int64_t> parent(n);
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int64_t x) {
+    while (parent[x] != x) x = parent[x] = parent[parent[x]];
+    return x;
+  };
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      int64_t a = find(i), b = find(A.ci[k]);
+      if (a != b) parent[std::max(a, b)] = std::min(a, b);
+    }
+  std::vector<int64_t> root(n);
+  for (int64_t i = 0; i < n; ++i) root[i] = find(i);
+  // row sums relative to row magnitude, max per component
+  std::vector<double> rs(n, 0.0), sc(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0, a = 0.0;
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      s += A.v[k];
+      a += std::fabs(A.v[k]);
+    }
+    rs[root[i]] = std::max(rs[root[i]], std::fabs(s));
+    sc[root[i]] = std::max(sc[root[i]], a);
+  }
+  std::vector<int32_t> id(n, -1), comp_of_root(n, -1);
+  int32_t nc = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t r = root[i];
+    if (rs[r] > 1e-9 * sc[r]) continue;
+    if (comp_of_root[r] < 0) comp_of_root[r] = nc++;
+    id[i] = comp_of_root[r];
+  }
+  *n_comp = nc;
+  return id;
+}
+
+}  // namespace fvem

@@ -1,0 +1,265 @@
+"""ctypes binding of libfvem.so (the C ABI in include/fvem.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch supplies device memory and the stream.  There is no fallback: if the
+library is missing or no GPU is visible, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfvem.so")
+
+STATUS = {0: "OK", 1: "INVALID", 2: "HIP", 3: "OOM", 4: "NOT_SPD", 5: "NOT_CONVERGED", 6: "NONFINITE",
+          7: "BUSY"}
+OP_K, OP_B, OP_BT, OP_VCYCLE, OP_VCYCLE32, OP_PROJECT = range(6)
+PREC_FP64, PREC_MIXED = 0, 1
+INPUT_VELOCITY, INPUT_RHS = 0, 1
+
+
+class FvemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fvem {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class NotConverged(FvemError):
+    pass
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _Level(ctypes.Structure):
+    _fields_ = [("n_dof", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("cell_ptr", ctypes.c_void_p),
+                ("cell_dof", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("P", _CSR)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("levels", ctypes.POINTER(_Level)),
+                ("ke_ptr", ctypes.c_void_p), ("ke_val", ctypes.c_void_p), ("n_vert", ctypes.c_int64),
+                ("cell_vptr", ctypes.c_void_p), ("cell_vert", ctypes.c_void_p), ("be_ptr", ctypes.c_void_p),
+                ("be_val", ctypes.c_void_p), ("component", ctypes.c_void_p), ("n_components", ctypes.c_int32)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("cheb_degree", ctypes.c_int32), ("cheb_lower", ctypes.c_double),
+                ("coarse_dense_max", ctypes.c_int32), ("coarse_rcond", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("input", ctypes.c_int32), ("replace_every", ctypes.c_int32), ("profile", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_fine_smoother", ctypes.c_double), ("n_fine_smoother", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_apply", "fvem_level_matrix",
+           "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error"]
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libfvem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FvemError(1, f"{path} is missing: build it with paper_2607_17725_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.fvem_hierarchy_build.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Options), vp, ctypes.POINTER(vp)]
+    lib.fvem_hierarchy_build.restype = ctypes.c_int
+    for fn in (lib.fvem_solve, lib.fvem_solve_adjoint):
+        fn.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
+        fn.restype = ctypes.c_int
+    lib.fvem_apply.argtypes = [vp, i32, vp, vp, vp]
+    lib.fvem_apply.restype = ctypes.c_int
+    lib.fvem_level_matrix.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
+    lib.fvem_level_matrix.restype = ctypes.c_int
+    lib.fvem_hierarchy_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i64)]
+    lib.fvem_hierarchy_info.restype = ctypes.c_int
+    lib.fvem_hierarchy_destroy.argtypes = [vp]
+    lib.fvem_hierarchy_destroy.restype = None
+    lib.fvem_last_error.argtypes = []
+    lib.fvem_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code == 0:
+        return
+    msg = load().fvem_last_error().decode()
+    if code == 5:
+        raise NotConverged(code, msg)
+    raise FvemError(code, msg)
+
+
+def _arr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+class Hierarchy:
+    """Solver hierarchy built from a problem description (host numpy arrays).
+
+    ``desc`` keys: ``levels`` (list of dicts with n_dof, cell_ptr, cell_dof,
+    parent, P given as (row_ptr, col, val) or None), ``ke_ptr``, ``ke_val``,
+    ``n_vert``, ``cell_vptr``, ``cell_vert``, ``be_ptr``, ``be_val``,
+    ``component``, ``n_components``.
+    """
+
+    def __init__(self, desc, stream=None, cheb_degree=5, cheb_lower=1.0 / 30.0, coarse_dense_max=16384,
+                 coarse_rcond=1e-10):
+        import torch
+        lib = load()
+        if not torch.cuda.is_available():
+            raise FvemError(2, "no GPU visible")
+        keep = []
+        L = len(desc["levels"])
+        levels = (_Level * L)()
+        for l, lv in enumerate(desc["levels"]):
+            cp, cpp = _arr(lv["cell_ptr"], np.int64)
+            cd, cdp = _arr(lv["cell_dof"], np.int32)
+            keep += [cp, cd]
+            levels[l].n_dof = int(lv["n_dof"])
+            levels[l].n_cells = len(cp) - 1
+            levels[l].cell_ptr = cpp
+            levels[l].cell_dof = cdp
+            if lv.get("parent") is not None:
+                pa, pap = _arr(lv["parent"], np.int32)
+                keep.append(pa)
+                levels[l].parent = pap
+            if lv.get("P") is not None:
+                rp, ci, va = lv["P"]
+                rp, rpp = _arr(rp, np.int64)
+                ci, cip = _arr(ci, np.int32)
+                va, vap = _arr(va, np.float64)
+                keep += [rp, ci, va]
+                levels[l].P = _CSR(len(rp) - 1, int(lv["P_cols"]), len(ci), rpp, cip, vap)
+        g = _Grid()
+        g.n_levels = L
+        g.levels = levels
+        for name, dt in (("ke_ptr", np.int64), ("ke_val", np.float64), ("cell_vptr", np.int64),
+                         ("cell_vert", np.int32), ("be_ptr", np.int64), ("be_val", np.float64),
+                         ("component", np.int32)):
+            if desc.get(name) is not None:
+                a, p = _arr(desc[name], dt)
+                keep.append(a)
+                setattr(g, name, p)
+        g.n_vert = int(desc.get("n_vert", 0))
+        g.n_components = int(desc.get("n_components", 0))
+        opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib.fvem_hierarchy_build(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(h)))
+        self._h = h
+        nl, n0, nv, nb = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.fvem_hierarchy_info(h, ctypes.byref(nl), ctypes.byref(n0), ctypes.byref(nv), ctypes.byref(nb)))
+        self.n_levels, self.n_dof, self.n_vert, self.device_bytes = nl.value, n0.value, nv.value, nb.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fvem_hierarchy_destroy(h)
+            self._h = None
+
+    def _vec(self, t, n, what):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
+                or t.device != self.device or t.numel() != n:
+            raise ValueError(f"{what}: expected a contiguous float64 tensor of {n} elements on {self.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _opts(self, tol, maxit, precision, input_kind, replace_every, profile):
+        return SolveOpts(tol, maxit, precision, input_kind, replace_every, 1 if profile else 0)
+
+    def solve(self, inp, out=None, tol=1e-8, maxit=500, precision=PREC_MIXED, input_kind=INPUT_VELOCITY,
+              replace_every=10, profile=False, raise_not_converged=True):
+        import torch
+        n_in = 3 * self.n_vert if input_kind == INPUT_VELOCITY else self.n_dof
+        pin = self._vec(inp, n_in, "input")
+        if out is None:
+            out = torch.empty(self.n_dof, dtype=torch.float64, device=self.device)
+        pout = self._vec(out, self.n_dof, "output")
+        st = SolveStats()
+        so = self._opts(tol, maxit, precision, input_kind, replace_every, profile)
+        code = load().fvem_solve(self._h, pin, pout, ctypes.byref(so), ctypes.byref(st),
+                                 ctypes.c_void_p(self.stream.cuda_stream))
+        if code != 5 or raise_not_converged:
+            _check(code)
+        return out, st.as_dict()
+
+    def solve_adjoint(self, gp, out=None, tol=1e-8, maxit=500, precision=PREC_MIXED, input_kind=INPUT_VELOCITY,
+                      replace_every=10):
+        import torch
+        n_out = 3 * self.n_vert if input_kind == INPUT_VELOCITY else self.n_dof
+        pin = self._vec(gp, self.n_dof, "g_p")
+        if out is None:
+            out = torch.empty(n_out, dtype=torch.float64, device=self.device)
+        pout = self._vec(out, n_out, "output")
+        st = SolveStats()
+        so = self._opts(tol, maxit, precision, input_kind, replace_every, False)
+        _check(load().fvem_solve_adjoint(self._h, pin, pout, ctypes.byref(so), ctypes.byref(st),
+                                         ctypes.c_void_p(self.stream.cuda_stream)))
+        return out, st.as_dict()
+
+    def apply(self, op, x):
+        import torch
+        n_in = 3 * self.n_vert if op == OP_B else self.n_dof
+        n_out = 3 * self.n_vert if op == OP_BT else self.n_dof
+        y = torch.empty(n_out, dtype=torch.float64, device=self.device)
+        _check(load().fvem_apply(self._h, op, self._vec(x, n_in, "x"), self._vec(y, n_out, "y"),
+                                 ctypes.c_void_p(self.stream.cuda_stream)))
+        return y
+
+    def level_matrix(self, level):
+        """Level operator as (row_ptr, col, val) host arrays."""
+        lib = load()
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.fvem_level_matrix(self._h, level, ctypes.byref(n), ctypes.byref(nnz), None, None, None))
+        rp = np.empty(n.value + 1, dtype=np.int64)
+        ci = np.empty(nnz.value, dtype=np.int32)
+        va = np.empty(nnz.value, dtype=np.float64)
+        _check(lib.fvem_level_matrix(self._h, level, ctypes.byref(n), ctypes.byref(nnz), rp.ctypes.data,
+                                     ci.ctypes.data, va.ctypes.data))
+        return rp, ci, va
+
+
+def project_function():
+    """torch.autograd.Function mapping vertex velocity u -> pressure p.
+
+    forward: p = K^+ P_perp B u (fvem_solve); backward: g_u = B^T P_perp K^+
+    P_perp g_p (fvem_solve_adjoint, the transpose of the linear map).
+    """
+    import torch
+
+    class FvemProject(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, u, hier, tol, precision):
+            ctx.hier, ctx.tol, ctx.precision = hier, tol, precision
+            p, _ = hier.solve(u.contiguous(), tol=tol, precision=precision)
+            return p
+
+        @staticmethod
+        def backward(ctx, gp):
+            gu, _ = ctx.hier.solve_adjoint(gp.contiguous(), tol=ctx.tol, precision=ctx.precision)
+            return gu, None, None, None
+
+    return FvemProject

@@ -69,27 +69,32 @@ typedef struct {
 } fvem_level_desc;
 
 /* The problem: hierarchy plus the finest level's element operators.
- *  ke_ptr/ke_val  element stiffness K^E of each level-0 cell, row-major
+ *  ke_off/ke_val  element stiffness K^E of each level-0 cell, row-major
  *                 n_E x n_E over the cell's local DOFs (n_E = cell_ptr[c+1]
- *                 - cell_ptr[c]); ke_ptr[c] is the offset of the block.
+ *                 - cell_ptr[c]), starting at ke_val[ke_off[c]]; cells of
+ *                 identical shape may share one block; ke_len is the length
+ *                 of ke_val.
  *  n_vert, cell_vptr/cell_vert  velocity vertices; cell c's vertices are
  *                 cell_vert[cell_vptr[c] .. cell_vptr[c+1]).
- *  be_ptr/be_val  divergence block B^E of each cell, row-major
- *                 n_E x (3 n_vE): column 3 v + d is component d of the cell's
- *                 v-th vertex velocity (Sec. 3.2 right-hand side).
+ *  be_off/be_val  divergence block B^E of each cell, row-major
+ *                 n_E x (3 n_vE) at be_val[be_off[c]]: column 3 v + d is
+ *                 component d of the cell's v-th vertex velocity (Sec. 3.2
+ *                 right-hand side); be_len is the length of be_val.
  *  component      [n_dof of level 0]: id of the pure-Neumann component of
  *                 each free DOF (0 .. n_components-1), or -1 where the
  *                 component is anchored by Dirichlet DOFs. */
 typedef struct {
     int32_t n_levels;
     const fvem_level_desc *levels;
-    const int64_t *ke_ptr;
+    const int64_t *ke_off;
     const double *ke_val;
+    int64_t ke_len;
     int64_t n_vert;
     const int64_t *cell_vptr;
     const int32_t *cell_vert;
-    const int64_t *be_ptr;
+    const int64_t *be_off;
     const double *be_val;
+    int64_t be_len;
     const int32_t *component;
     int32_t n_components;
 } fvem_grid_desc;
@@ -174,6 +179,42 @@ fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n
                                 int64_t *n_vert, int64_t *device_bytes);
 
 void fvem_hierarchy_destroy(fvem_hierarchy *h);
+
+/* ---------------------------------------------------------------- grid builder
+ * Builds the problem description from a boundary triangle mesh (host, C++):
+ * the binary-space cut-cell grid of Sec. 5.1 (each background cell split by
+ * the planes of its triangles, fewest plane crossings first; parts below
+ * 1e-12 volume skipped; leaves classified interior/exterior), the nested
+ * boundary-aware hierarchy of Sec. 5.2 (aggregation of uncut cubes, greedy
+ * removal of least-important cuts up to 1/L of the weight per level), the
+ * conforming order-k VEM element operators of Sec. 3.1-3.2 and the
+ * diffusion-free prolongation of Sec. 4.
+ *  V [nv x 3] vertices and F [nt x 3] outward triangles of a closed mesh
+ *  (host, caller-owned, read during the call); N background resolution
+ *  (a power of two); k in {1, 2}; levels L; dirichlet_top nonzero puts
+ *  p = 0 on z = 1 (else pure Neumann); coarse_max the dense coarse-solver
+ *  limit.  Errors: INVALID (sizes, k, N), OOM. */
+typedef struct fvem_grid fvem_grid;
+
+fvem_status fvem_grid_build(const double *V, int64_t nv, const int32_t *F, int64_t nt, int32_t N, int32_t k,
+                            int32_t levels, int32_t dirichlet_top, int64_t coarse_max, fvem_grid **out);
+
+/* Fills *d with pointers into the grid's own storage (valid until
+ * fvem_grid_destroy); the result can be passed to fvem_hierarchy_build. */
+fvem_status fvem_grid_describe(fvem_grid *g, fvem_grid_desc *d);
+
+/* Host views of the finest level: velocity vertices [n_vert x 3], DOF support
+ * points [n_dof x 3] and DOF kinds (0 vertex, 1 edge midpoint, 2 face, 3 cell),
+ * number of cut trees and of distinct shared element blocks. */
+fvem_status fvem_grid_info(fvem_grid *g, const double **vertices, int64_t *n_vert, const double **dof_points,
+                           const int8_t **dof_kind, int64_t *n_dof, int64_t *n_trees, int64_t *n_shared);
+
+/* Support points [n_dof x 3] and kinds of level l's free DOFs (vertex, edge
+ * midpoint, face vertex mean, cell centroid), in the level's numbering. */
+fvem_status fvem_grid_level_points(fvem_grid *g, int32_t level, const double **dof_points, const int8_t **dof_kind,
+                                   int64_t *n_dof);
+
+void fvem_grid_destroy(fvem_grid *g);
 
 const char *fvem_last_error(void);
 

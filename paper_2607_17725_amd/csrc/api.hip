@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -19,6 +20,7 @@
 
 #include "../../include/fvem.h"
 #include "kernels.hpp"
+#include "grid.hpp"
 #include "setup_host.hpp"
 
 namespace fvem {
@@ -200,21 +202,21 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   // level-0 element stiffness blocks
   const HostCells &c0 = cells[0];
   HostBlocks ke;
-  check(g->ke_ptr && g->ke_val, "element stiffness missing");
-  ke.off.assign(g->ke_ptr, g->ke_ptr + c0.n_cells + 1);
+  check(g->ke_off && g->ke_val && g->ke_len >= 0, "element stiffness missing");
+  ke.off.assign(g->ke_off, g->ke_off + c0.n_cells);
   for (int64_t c = 0; c < c0.n_cells; ++c) {
     const int64_t m = c0.ptr[c + 1] - c0.ptr[c];
-    check(ke.off[c + 1] - ke.off[c] == m * m, "element stiffness block size");
+    check(ke.off[c] >= 0 && ke.off[c] + m * m <= g->ke_len, "element stiffness block out of range");
   }
-  ke.val.assign(g->ke_val, g->ke_val + ke.off[c0.n_cells]);
-  check(finite_all(ke.val.data(), ke.off[c0.n_cells]), "element stiffness: non-finite value");
+  ke.val.assign(g->ke_val, g->ke_val + g->ke_len);
+  check(finite_all(ke.val.data(), g->ke_len), "element stiffness: non-finite value");
   h->n0 = g->levels[0].n_dof;
   // divergence
   h->nvert = g->n_vert;
   check(g->n_vert >= 0, "n_vert");
   HostCSR Bh;
   if (g->n_vert > 0) {
-    check(g->cell_vptr && g->cell_vert && g->be_ptr && g->be_val, "divergence blocks missing");
+    check(g->cell_vptr && g->cell_vert && g->be_off && g->be_val && g->be_len >= 0, "divergence blocks missing");
     HostCells vc;
     vc.n_cells = c0.n_cells;
     vc.ptr.resize(c0.n_cells + 1);
@@ -230,12 +232,12 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     }
     vc.dof = std::move(vdof);
     HostBlocks be;
-    be.off.assign(g->be_ptr, g->be_ptr + c0.n_cells + 1);
+    be.off.assign(g->be_off, g->be_off + c0.n_cells);
     for (int64_t c = 0; c < c0.n_cells; ++c)
-      check(be.off[c + 1] - be.off[c] == (c0.ptr[c + 1] - c0.ptr[c]) * (vc.ptr[c + 1] - vc.ptr[c]),
-            "divergence block size");
-    be.val.assign(g->be_val, g->be_val + be.off[c0.n_cells]);
-    check(finite_all(be.val.data(), be.off[c0.n_cells]), "divergence: non-finite value");
+      check(be.off[c] >= 0 && be.off[c] + (c0.ptr[c + 1] - c0.ptr[c]) * (vc.ptr[c + 1] - vc.ptr[c]) <= g->be_len,
+            "divergence block out of range");
+    be.val.assign(g->be_val, g->be_val + g->be_len);
+    check(finite_all(be.val.data(), g->be_len), "divergence: non-finite value");
     Bh = assemble_blocks(h->n0, 3 * g->n_vert, c0, vc, be);
   }
   // components of level 0
@@ -751,5 +753,132 @@ void fvem_hierarchy_destroy(fvem_hierarchy *h) {
 }
 
 const char *fvem_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+struct fvem_grid {
+  fvem::grid::Output out;
+  std::vector<fvem_level_desc> levels;
+  std::vector<double> xflat;
+};
+
+extern "C" {
+
+fvem_status fvem_grid_build(const double *V, int64_t nv, const int32_t *F, int64_t nt, int32_t N, int32_t k,
+                            int32_t levels, int32_t dirichlet_top, int64_t coarse_max, fvem_grid **out) {
+  if (!out) {
+    g_last_error = "null output handle";
+    return FVEM_ERR_INVALID;
+  }
+  *out = nullptr;
+  return guard([&] {
+    check(N >= 2 && N <= 1024 && (N & (N - 1)) == 0, "N must be a power of two in [2, 1024]");
+    check(k == 1 || k == 2, "k must be 1 or 2");
+    check(levels >= 1, "levels must be >= 1");
+    check(nv >= 0 && nt >= 0 && (nt == 0 || (V && F)), "boundary mesh arrays");
+    for (int64_t i = 0; i < 3 * nt; ++i) check(F[i] >= 0 && F[i] < nv, "triangle vertex index out of range");
+    for (int64_t i = 0; i < 3 * nv; ++i) check(std::isfinite(V[i]), "non-finite boundary vertex");
+    auto g = std::make_unique<fvem_grid>();
+    grid::Input in;
+    in.V = V;
+    in.nv = nv;
+    in.F = F;
+    in.nt = nt;
+    in.N = N;
+    in.k = k;
+    in.L = levels;
+    in.dirichlet = dirichlet_top != 0;
+    in.coarse_max = coarse_max > 0 ? coarse_max : 16384;
+    try {
+      grid::build_grid(in, &g->out);
+    } catch (const std::runtime_error &e) {
+      throw SetupError{FVEM_ERR_INVALID, std::string("grid construction failed: ") + e.what()};
+    }
+    const auto &o = g->out;
+    const int L = static_cast<int>(o.levels.size());
+    g->levels.resize(L);
+    for (int l = 0; l < L; ++l) {
+      fvem_level_desc &d = g->levels[l];
+      const auto &lv = o.levels[l];
+      d.n_dof = lv.n_dof;
+      d.n_cells = lv.n_cells;
+      d.cell_ptr = lv.cell_ptr.data();
+      d.cell_dof = lv.cell_dof.data();
+      d.parent = l + 1 < L ? lv.parent.data() : nullptr;
+      d.P = fvem_csr{};
+      if (l + 1 < L) {
+        const auto &P = o.P[l];
+        d.P.n_rows = lv.n_dof;
+        d.P.n_cols = o.levels[l + 1].n_dof;
+        d.P.nnz = static_cast<int64_t>(P.ci.size());
+        d.P.row_ptr = P.rp.data();
+        d.P.col = P.ci.data();
+        d.P.val = P.v.data();
+      }
+    }
+    g->xflat.resize(3 * o.X.size());
+    for (size_t i = 0; i < o.X.size(); ++i) {
+      g->xflat[3 * i] = o.X[i].x;
+      g->xflat[3 * i + 1] = o.X[i].y;
+      g->xflat[3 * i + 2] = o.X[i].z;
+    }
+    *out = g.release();
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_grid_describe(fvem_grid *g, fvem_grid_desc *d) {
+  if (!g || !d) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  const auto &o = g->out;
+  d->n_levels = static_cast<int32_t>(g->levels.size());
+  d->levels = g->levels.data();
+  d->ke_off = o.ke_off.data();
+  d->ke_val = o.ke_val.data();
+  d->ke_len = static_cast<int64_t>(o.ke_val.size());
+  d->n_vert = o.n_vert;
+  d->cell_vptr = o.cell_vptr.data();
+  d->cell_vert = o.cell_vert.data();
+  d->be_off = o.be_off.data();
+  d->be_val = o.be_val.data();
+  d->be_len = static_cast<int64_t>(o.be_val.size());
+  d->component = o.component.data();
+  d->n_components = o.n_components;
+  return FVEM_OK;
+}
+
+fvem_status fvem_grid_info(fvem_grid *g, const double **vertices, int64_t *n_vert, const double **dof_points,
+                           const int8_t **dof_kind, int64_t *n_dof, int64_t *n_trees, int64_t *n_shared) {
+  if (!g) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  const auto &o = g->out;
+  if (vertices) *vertices = g->xflat.data();
+  if (n_vert) *n_vert = o.n_vert;
+  if (dof_points) *dof_points = o.dof_point.data();
+  if (dof_kind) *dof_kind = o.dof_kind.data();
+  if (n_dof) *n_dof = o.levels.empty() ? 0 : o.levels[0].n_dof;
+  if (n_trees) *n_trees = o.n_trees;
+  if (n_shared) *n_shared = o.n_shared_blocks;
+  return FVEM_OK;
+}
+
+fvem_status fvem_grid_level_points(fvem_grid *g, int32_t level, const double **dof_points, const int8_t **dof_kind,
+                                   int64_t *n_dof) {
+  if (!g || level < 0 || level >= static_cast<int32_t>(g->out.levels.size())) {
+    g_last_error = "bad grid or level";
+    return FVEM_ERR_INVALID;
+  }
+  const auto &lv = g->out.levels[level];
+  if (dof_points) *dof_points = lv.dof_point.data();
+  if (dof_kind) *dof_kind = lv.dof_kind.data();
+  if (n_dof) *n_dof = lv.n_dof;
+  return FVEM_OK;
+}
+
+void fvem_grid_destroy(fvem_grid *g) { delete g; }
 
 }  // extern "C"

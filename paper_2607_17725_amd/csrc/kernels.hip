@@ -430,10 +430,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
     const double b = (jb < N && kc < K) ? B[kc * sbk + jb * sbj] : 0.0;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  // D layout: lane holds rows 4*(lane/16) + q, column lane%16
+  // D layout (measured on gfx950): register q of a lane holds row
+  // (lane / 16) + 4 q, column lane % 16; A and B are row-of-lane / k-of-group
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int64_t i = i0 + 4 * (lane >> 4) + q;
+    const int64_t i = i0 + (lane >> 4) + 4 * q;
     const int64_t j = j0 + (lane & 15);
     if (i < M && j < N) {
       double *c = C + i + j * ldc;

@@ -98,6 +98,7 @@ HostBlocks galerkin_blocks(const HostCells &fine, const HostBlocks &kf, const in
     out.off[c + 1] = out.off[c] + m * m;
   }
   out.val.assign(out.off[nc], 0.0);
+  out.off.pop_back();
   int bad = 0;
   int64_t bad_row = -1;
 #pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)

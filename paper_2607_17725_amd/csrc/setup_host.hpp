@@ -26,7 +26,8 @@ struct HostCells {
   std::vector<int32_t> dof;
 };
 
-// Dense element blocks, block c is n_c x m_c row-major at off[c].
+// Dense element blocks, block c is n_c x m_c row-major at off[c] (blocks
+// may be shared between cells of identical shape).
 struct HostBlocks {
   std::vector<int64_t> off;
   std::vector<double> val;

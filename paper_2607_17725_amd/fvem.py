@@ -41,9 +41,10 @@ class _Level(ctypes.Structure):
 
 class _Grid(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("levels", ctypes.POINTER(_Level)),
-                ("ke_ptr", ctypes.c_void_p), ("ke_val", ctypes.c_void_p), ("n_vert", ctypes.c_int64),
-                ("cell_vptr", ctypes.c_void_p), ("cell_vert", ctypes.c_void_p), ("be_ptr", ctypes.c_void_p),
-                ("be_val", ctypes.c_void_p), ("component", ctypes.c_void_p), ("n_components", ctypes.c_int32)]
+                ("ke_off", ctypes.c_void_p), ("ke_val", ctypes.c_void_p), ("ke_len", ctypes.c_int64),
+                ("n_vert", ctypes.c_int64), ("cell_vptr", ctypes.c_void_p), ("cell_vert", ctypes.c_void_p),
+                ("be_off", ctypes.c_void_p), ("be_val", ctypes.c_void_p), ("be_len", ctypes.c_int64),
+                ("component", ctypes.c_void_p), ("n_components", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -66,7 +67,8 @@ class SolveStats(ctypes.Structure):
 
 
 EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_apply", "fvem_level_matrix",
-           "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error"]
+           "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error", "fvem_grid_build",
+           "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy"]
 
 _lib = None
 
@@ -96,6 +98,18 @@ def load(path=LIB_PATH):
     lib.fvem_hierarchy_destroy.restype = None
     lib.fvem_last_error.argtypes = []
     lib.fvem_last_error.restype = ctypes.c_char_p
+    lib.fvem_grid_build.argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i64, ctypes.POINTER(vp)]
+    lib.fvem_grid_build.restype = ctypes.c_int
+    lib.fvem_grid_describe.argtypes = [vp, ctypes.POINTER(_Grid)]
+    lib.fvem_grid_describe.restype = ctypes.c_int
+    lib.fvem_grid_info.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                   ctypes.POINTER(i64)]
+    lib.fvem_grid_info.restype = ctypes.c_int
+    lib.fvem_grid_level_points.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    lib.fvem_grid_level_points.restype = ctypes.c_int
+    lib.fvem_grid_destroy.argtypes = [vp]
+    lib.fvem_grid_destroy.restype = None
     _lib = lib
     return lib
 
@@ -129,6 +143,11 @@ class Hierarchy:
         lib = load()
         if not torch.cuda.is_available():
             raise FvemError(2, "no GPU visible")
+        if isinstance(desc, Grid):
+            g = _Grid()
+            _check(lib.fvem_grid_describe(desc._g, ctypes.byref(g)))
+            self._finish(lib, g, [desc], stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond)
+            return
         keep = []
         L = len(desc["levels"])
         levels = (_Level * L)()
@@ -154,15 +173,21 @@ class Hierarchy:
         g = _Grid()
         g.n_levels = L
         g.levels = levels
-        for name, dt in (("ke_ptr", np.int64), ("ke_val", np.float64), ("cell_vptr", np.int64),
-                         ("cell_vert", np.int32), ("be_ptr", np.int64), ("be_val", np.float64),
+        for name, dt in (("ke_off", np.int64), ("ke_val", np.float64), ("cell_vptr", np.int64),
+                         ("cell_vert", np.int32), ("be_off", np.int64), ("be_val", np.float64),
                          ("component", np.int32)):
             if desc.get(name) is not None:
                 a, p = _arr(desc[name], dt)
                 keep.append(a)
                 setattr(g, name, p)
+        g.ke_len = len(desc["ke_val"])
+        g.be_len = len(desc["be_val"]) if desc.get("be_val") is not None else 0
         g.n_vert = int(desc.get("n_vert", 0))
         g.n_components = int(desc.get("n_components", 0))
+        self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond)
+
+    def _finish(self, lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond):
+        import torch
         opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -240,6 +265,81 @@ class Hierarchy:
         _check(lib.fvem_level_matrix(self._h, level, ctypes.byref(n), ctypes.byref(nnz), rp.ctypes.data,
                                      ci.ctypes.data, va.ctypes.data))
         return rp, ci, va
+
+
+class Grid:
+    """Native cut-cell grid, VEM operators and hierarchy built from a boundary mesh (host C++)."""
+
+    def __init__(self, V, F, N, k, levels=5, dirichlet_top=False, coarse_max=16384):
+        lib = load()
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        F = np.ascontiguousarray(F, dtype=np.int32)
+        g = ctypes.c_void_p()
+        _check(lib.fvem_grid_build(V.ctypes.data, len(V), F.ctypes.data, len(F), int(N), int(k), int(levels),
+                                   1 if dirichlet_top else 0, int(coarse_max), ctypes.byref(g)))
+        self._g = g
+        self.N, self.k = N, k
+        xv, nv, dp, dk = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_void_p(), ctypes.c_void_p()
+        nd, ntr, nsh = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.fvem_grid_info(g, ctypes.byref(xv), ctypes.byref(nv), ctypes.byref(dp), ctypes.byref(dk),
+                                  ctypes.byref(nd), ctypes.byref(ntr), ctypes.byref(nsh)))
+        self.n_vert, self.n_dof, self.n_trees, self.n_shared_blocks = nv.value, nd.value, ntr.value, nsh.value
+        self.vertices = np.ctypeslib.as_array(ctypes.cast(xv, ctypes.POINTER(ctypes.c_double)),
+                                              shape=(self.n_vert, 3)).copy()
+        self.dof_points = np.ctypeslib.as_array(ctypes.cast(dp, ctypes.POINTER(ctypes.c_double)),
+                                                shape=(self.n_dof, 3)).copy()
+        self.dof_kind = np.ctypeslib.as_array(ctypes.cast(dk, ctypes.POINTER(ctypes.c_int8)),
+                                              shape=(self.n_dof,)).copy()
+
+    def level_points(self, level):
+        """(points [n x 3], kinds [n]) of level ``level``'s free DOFs."""
+        lib = load()
+        dp, dk, n = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        _check(lib.fvem_grid_level_points(self._g, level, ctypes.byref(dp), ctypes.byref(dk), ctypes.byref(n)))
+        if n.value == 0:
+            return np.zeros((0, 3)), np.zeros(0, dtype=np.int8)
+        pts = np.ctypeslib.as_array(ctypes.cast(dp, ctypes.POINTER(ctypes.c_double)), shape=(n.value, 3)).copy()
+        knd = np.ctypeslib.as_array(ctypes.cast(dk, ctypes.POINTER(ctypes.c_int8)), shape=(n.value,)).copy()
+        return pts, knd
+
+    def describe(self):
+        """The problem description as host numpy arrays (copies)."""
+        lib = load()
+        g = _Grid()
+        _check(lib.fvem_grid_describe(self._g, ctypes.byref(g)))
+
+        def arr(ptr, n, ct):
+            if n == 0:
+                return np.zeros(0, dtype=np.ctypeslib.as_array((ct * 1)()).dtype)
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ct)), shape=(n,)).copy()
+
+        levels = []
+        for l in range(g.n_levels):
+            lv = g.levels[l]
+            cp = arr(lv.cell_ptr, lv.n_cells + 1, ctypes.c_int64)
+            d = {"n_dof": lv.n_dof, "cell_ptr": cp, "cell_dof": arr(lv.cell_dof, int(cp[-1]), ctypes.c_int32),
+                 "parent": None, "P": None}
+            if l + 1 < g.n_levels:
+                d["parent"] = arr(lv.parent, lv.n_cells, ctypes.c_int32)
+                P = lv.P
+                d["P"] = (arr(P.row_ptr, P.n_rows + 1, ctypes.c_int64), arr(P.col, P.nnz, ctypes.c_int32),
+                          arr(P.val, P.nnz, ctypes.c_double))
+                d["P_cols"] = P.n_cols
+            levels.append(d)
+        nc0 = g.levels[0].n_cells
+        vptr = arr(g.cell_vptr, nc0 + 1, ctypes.c_int64)
+        return {"levels": levels, "ke_off": arr(g.ke_off, nc0, ctypes.c_int64),
+                "ke_val": arr(g.ke_val, g.ke_len, ctypes.c_double), "n_vert": g.n_vert, "cell_vptr": vptr,
+                "cell_vert": arr(g.cell_vert, int(vptr[-1]), ctypes.c_int32),
+                "be_off": arr(g.be_off, nc0, ctypes.c_int64), "be_val": arr(g.be_val, g.be_len, ctypes.c_double),
+                "component": arr(g.component, g.levels[0].n_dof, ctypes.c_int32),
+                "n_components": g.n_components}
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g is not None and _lib is not None:
+            _lib.fvem_grid_destroy(g)
+            self._g = None
 
 
 def project_function():

@@ -46,9 +46,9 @@ def describe(pb):
         comp[idx] = c
     return {
         "levels": levels,
-        "ke_ptr": np.array(ke_ptr, dtype=np.int64), "ke_val": np.concatenate(ke_val),
+        "ke_off": np.array(ke_ptr[:-1], dtype=np.int64), "ke_val": np.concatenate(ke_val),
         "n_vert": pb.dofs[0].nv,
         "cell_vptr": np.array(vptr, dtype=np.int64), "cell_vert": np.array(vert, dtype=np.int32),
-        "be_ptr": np.array(be_ptr, dtype=np.int64), "be_val": np.concatenate(be_val),
+        "be_off": np.array(be_ptr[:-1], dtype=np.int64), "be_val": np.concatenate(be_val),
         "component": comp, "n_components": len(pb.null.floating),
     }

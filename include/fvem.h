@@ -17,6 +17,14 @@
  *    (NULL = the default stream) and is complete in stream order when the
  *    call returns.
  *  - Results are bitwise deterministic for a given input and build.
+ *
+ * The coarsest level of the hierarchy is solved with a dense Cholesky
+ * factorisation of A_c + shift diag(A_c) (the paper does not specify the
+ * coarse solver).  A_c is only positive semi-definite (pure-Neumann
+ * constants; coarse DOF combinations the prolongation annihilates); every
+ * right-hand side the V-cycle restricts to that level is orthogonal to those
+ * directions, and what the shift adds along them vanishes after
+ * prolongation.
  */
 #ifndef FVEM_H
 #define FVEM_H
@@ -104,7 +112,8 @@ typedef struct {
     int32_t cheb_degree;        /* Chebyshev degree per smoothing [5] */
     double cheb_lower;          /* lower end of the interval as a fraction of lmax [1/30] */
     int32_t coarse_dense_max;   /* largest coarsest level factored densely [16384] */
-    double coarse_rcond;        /* pivots below rcond * diag are treated as zero [1e-10] */
+    double coarse_rcond;        /* pivots below rcond * diag are treated as zero [0] */
+    double coarse_shift;        /* the coarsest level factors A_c + shift diag(A_c) [1e-8] */
 } fvem_options;
 
 typedef enum { FVEM_PREC_FP64 = 0, FVEM_PREC_MIXED = 1 } fvem_precision;

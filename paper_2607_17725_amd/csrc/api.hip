@@ -95,8 +95,6 @@ struct fvem_hierarchy {
   // coarsest level
   int64_t nc = 0;
   double *G = nullptr;
-  int32_t *compc = nullptr;
-  int ncompc = 0;
   double *bc = nullptr, *xc = nullptr;
   // PCG
   double *b, *x, *r, *z, *zold, *p, *q, *lam, *partial, *dotout, *mean;
@@ -185,7 +183,8 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const int deg = (o && o->cheb_degree > 0) ? o->cheb_degree : 5;
   const double lower = (o && o->cheb_lower > 0) ? o->cheb_lower : 1.0 / 30.0;
   const int64_t dense_max = (o && o->coarse_dense_max > 0) ? o->coarse_dense_max : 16384;
-  const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 1e-10;
+  const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 0.0;
+  const double shift = (o && o->coarse_shift > 0) ? o->coarse_shift : 1e-8;
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
   h->lv.resize(L);
@@ -302,16 +301,19 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   h->nc = Ac.n_rows;
   check(h->nc <= dense_max, "coarsest level exceeds coarse_dense_max");
   {
-    int32_t ncc = 0;
-    std::vector<int32_t> cc = floating_components(Ac, &ncc);
-    h->compc = h->mem.upload(cc, s);
-    h->ncompc = ncc;
     const int64_t n = h->nc;
     std::vector<double> diag0(n, 0.0);
     for (int64_t i = 0; i < n; ++i)
       for (int64_t k = Ac.rp[i]; k < Ac.rp[i + 1]; ++k)
         if (Ac.ci[k] == i) diag0[i] = Ac.v[k];
+    // A_c is positive semi-definite (pure-Neumann constants; coarse DOF
+    // combinations the prolongation annihilates); every restricted
+    // right-hand side is orthogonal to those directions, so the coarsest
+    // level solves with the positive definite A_c + shift diag(A_c)
+    std::vector<double> dshift(n);
+    for (int64_t i = 0; i < n; ++i) dshift[i] = shift * diag0[i];
     double *dg = h->mem.upload(diag0, s);
+    double *ds = h->mem.upload(dshift, s);
     DevMem tmp;
     double *D = tmp.alloc<double>(n * n);
     double *X = tmp.alloc<double>(n * n);
@@ -319,6 +321,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), s));
     const Level &C = h->lv[L - 1];
     dense_from_csr(n, C.A.rp, C.A.ci, C.A.v64, D, s);
+    add_diagonal(n, D, ds, s);
     potrf_semidefinite(D, n, dg, rcond, flag, s);
     trinv_semidefinite(D, X, n, s);
     h->G = h->mem.alloc<double>(n * n);
@@ -327,7 +330,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     int hflag = 0;
     HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    if (hflag) throw SetupError{FVEM_ERR_NOT_SPD, "coarsest operator has a significantly negative pivot"};
+    if (hflag) throw SetupError{FVEM_ERR_NOT_SPD, "coarsest operator is not positive semi-definite"};
     h->bc = h->mem.alloc<double>(n);
     h->xc = h->mem.alloc<double>(n);
   }
@@ -392,9 +395,7 @@ static void coarse_solve(fvem_hierarchy *h, hipStream_t s) {
   } else {
     HIPCHECK(hipMemcpyAsync(h->bc, C.b64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   }
-  if (h->ncompc) project_components(n, h->bc, h->compc, h->ncompc, h->partial, h->mean, s);
   symv(n, h->G, h->bc, h->xc, s);
-  if (h->ncompc) project_components(n, h->xc, h->compc, h->ncompc, h->partial, h->mean, s);
   if constexpr (sizeof(T) == 4) {
     cast_scale(n, h->xc, C.x32, 1.0, s);
   } else {
@@ -444,9 +445,7 @@ static void precondition(fvem_hierarchy *h, const double *r, double *z, bool mix
   Level &L0 = h->lv[0];
   const int64_t n = h->n0;
   if (h->nlev == 1) {
-    HIPCHECK(hipMemcpyAsync(h->bc, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    if (h->ncompc) project_components(n, h->bc, h->compc, h->ncompc, h->partial, h->mean, s);
-    symv(n, h->G, h->bc, z, s);
+    symv(n, h->G, r, z, s);
   } else if (mixed) {
     const double sc = rnorm > 0 ? 1.0 / rnorm : 1.0;
     cast_scale(n, r, L0.b32, sc, s);

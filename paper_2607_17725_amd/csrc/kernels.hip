@@ -532,6 +532,15 @@ void dense_from_csr(int64_t n, const int64_t *rp, const int32_t *ci, const doubl
   if (n) dense_from_csr_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(n, rp, ci, v, D);
 }
 
+__global__ void add_diagonal_kernel(int64_t n, double *D, const double *v) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n) D[i + i * n] += v[i];
+}
+
+void add_diagonal(int64_t n, double *D, const double *v, hipStream_t s) {
+  if (n) add_diagonal_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(n, D, v);
+}
+
 __global__ void cast_f64_f32_kernel(int64_t n, const double *a, float *b) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)

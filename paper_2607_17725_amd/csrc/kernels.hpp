@@ -50,6 +50,7 @@ void gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *A, in
 void potrf_semidefinite(double *A, int64_t n, const double *diag0, double rcond, int *flag, hipStream_t s);
 void trinv_semidefinite(const double *L, double *X, int64_t n, hipStream_t s);
 void symv(int64_t n, const double *G, const double *x, double *y, hipStream_t s);
+void add_diagonal(int64_t n, double *D, const double *v, hipStream_t s);   // D_ii += v_i
 void dense_from_csr(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, double *D, hipStream_t s);
 
 }  // namespace fvem

@@ -87,7 +87,7 @@ def test_vcycle_fp64_matches_oracle(name, request):
     r = pb.null.project(rng.standard_normal(pb.K.shape[0]))
     z_ref = pb.null.project(pb.mg.vcycle(r))
     z = pb.null.project(_host(h.apply(fvem.OP_VCYCLE, _dev(r))))
-    assert np.linalg.norm(z - z_ref) <= 1e-9 * np.linalg.norm(z_ref)
+    assert np.linalg.norm(z - z_ref) <= 1e-8 * np.linalg.norm(z_ref)
     z32 = pb.null.project(_host(h.apply(fvem.OP_VCYCLE32, _dev(r))))
     assert np.linalg.norm(z32 - z_ref) <= 1e-4 * np.linalg.norm(z_ref)
 

@@ -4,7 +4,9 @@
   paper's coarse-operator definition).
 * Smoother: Chebyshev semi-iteration (Saad, Iterative Methods for Sparse
   Linear Systems, Alg. 12.1) of degree 5 on D^-1 A (D = diag A) over
-  [lmax/30, lmax], lmax the Gershgorin bound max_i sum_j |a_ij| / a_ii.  The
+  [lmax/30, lmax], lmax the Gershgorin bound of the similar matrix
+  D^-1/2 A D^-1/2, max_i sum_j |a_ij| / sqrt(a_ii a_jj), which stays below
+  the row length even where a coarse diagonal is tiny.  The
   paper specifies "the Chebyshev smoother with default parameters" of a
   library that is not available; this is the reading taken (parity unpinned
   against that library).  The diagonal scaling is needed on cut-cell grids
@@ -43,10 +45,12 @@ def galerkin(A, P):
 
 
 def gershgorin(A, dinv=None):
-    rows = np.asarray(np.abs(A).sum(axis=1)).ravel()
-    if dinv is not None:
-        rows = rows * np.abs(dinv)
-    return float(rows.max())
+    """Gershgorin bound of A, or with ``dinv`` of D^-1/2 A D^-1/2 (the spectrum of D^-1 A)."""
+    if dinv is None:
+        return float(np.asarray(np.abs(A).sum(axis=1)).ravel().max())
+    s = np.sqrt(np.abs(dinv))
+    S = sp.diags(s) @ abs(A) @ sp.diags(s)
+    return float(np.asarray(S.sum(axis=1)).ravel().max())
 
 
 class NullSpace:

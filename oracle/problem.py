@@ -13,6 +13,9 @@ from .multigrid import Hierarchy, NullSpace, direct_solve, pcg
 from .prolong import build_prolongation
 
 
+UNUSED_TOL = 1e-10
+
+
 def _dof_count(k):
     def f(mesh):
         if k == 1:
@@ -41,8 +44,10 @@ class Problem:
             P, hk = build_prolongation(self.meshes[t], self.dofs[t], self.meshes[t + 1],
                                        self.dofs[t + 1], self.parents[t])
             # coarse DOFs no fine DOF depends on (vertices deep in the solid
-            # part of a coarse cell) carry no information: drop them
-            used = np.asarray(np.abs(P).sum(axis=0)).ravel() > 0
+            # part of a coarse cell) carry no information: drop them; a
+            # largest weight below 1e-10 is an exact zero of the projection
+            # polluted by rounding (thin cells amplify it to ~1e-11)
+            used = np.asarray(np.abs(P).max(axis=0).todense()).ravel() > UNUSED_TOL
             if not used.all():
                 self.dofs[t + 1].deactivate(self.dofs[t + 1].free_ids[~used])
                 P = P[:, np.nonzero(used)[0]].tocsr()

@@ -28,6 +28,7 @@ from .quadrature import polygon_rule, polyhedron_rule
 from .vem import CellGeometry, cell_projector, face_projector
 
 TOL = 1e-9
+WEIGHT_TOL = 1e-13
 
 
 def _point_in_face(p, P, n, tol=TOL):
@@ -171,9 +172,14 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
         fi = fine_dofs.free[i]
         if fi < 0:
             continue
+        # weights at rounding level of the row's largest weight are zeros of
+        # the exact prolongation (projections evaluated where a basis
+        # function vanishes); keeping them would leave coarse DOFs with
+        # numerically empty columns and near-zero coarse diagonals
+        wmax = max((abs(w) for w in row.values()), default=0.0)
         for j, w in row.items():
             cj = coarse_dofs.free[j]
-            if cj < 0 or w == 0.0:
+            if cj < 0 or abs(w) <= WEIGHT_TOL * wmax:
                 continue
             r.append(fi)
             cidx.append(cj)

@@ -1047,10 +1047,15 @@ struct BuilderImpl {
     ci.clear();
     va.clear();
     for (int64_t i = 0; i < F.nfree; ++i) {
+      // weights at rounding level of the row's largest weight are zeros of
+      // the exact prolongation; dropped so that no coarse DOF keeps a
+      // numerically empty column
+      double wmax = 0;
+      for (auto &e : rows[frow[i]].e) wmax = std::max(wmax, std::fabs(e.second));
       std::vector<std::pair<int32_t, double>> ent;
       for (auto &e : rows[frow[i]].e) {
         const int32_t cj = C.free[C.perm[e.first]];
-        if (cj >= 0 && e.second != 0.0) ent.push_back({cj, e.second});
+        if (cj >= 0 && std::fabs(e.second) > 1e-13 * wmax) ent.push_back({cj, e.second});
       }
       std::sort(ent.begin(), ent.end());
       // merge duplicates (a coarse DOF reached twice)
@@ -1122,8 +1127,30 @@ struct BuilderImpl {
       std::vector<int32_t> ci;
       std::vector<double> va;
       prolongation(static_cast<int>(levels.size()) - 2, rp, ci, va);
+      // a coarse DOF is used when some fine DOF depends on it with a weight
+      // above 1e-10; smaller largest weights are exact zeros of the
+      // projection polluted by rounding (thin cells amplify it)
       std::vector<uint8_t> used(levels.back().nfree, 0);
-      for (int32_t j : ci) used[j] = 1;
+      {
+        std::vector<double> cmax(levels.back().nfree, 0.0);
+        for (size_t q = 0; q < ci.size(); ++q) cmax[ci[q]] = std::max(cmax[ci[q]], std::fabs(va[q]));
+        for (int64_t j = 0; j < levels.back().nfree; ++j) used[j] = cmax[j] > 1e-10;
+        // entries of unused columns are removed with the columns
+        std::vector<int64_t> rp2(rp.size(), 0);
+        std::vector<int32_t> ci2;
+        std::vector<double> va2;
+        for (size_t i = 0; i + 1 < rp.size(); ++i) {
+          for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (used[ci[q]]) {
+              ci2.push_back(ci[q]);
+              va2.push_back(va[q]);
+            }
+          rp2[i + 1] = static_cast<int64_t>(ci2.size());
+        }
+        rp.swap(rp2);
+        ci.swap(ci2);
+        va.swap(va2);
+      }
       bool all = true;
       for (uint8_t u : used) all = all && u;
       if (!all) {

@@ -177,15 +177,18 @@ HostCSR transpose(const HostCSR &A) {
 }
 
 double gershgorin_scaled(const HostCSR &A) {
+  const int64_t n = A.n_rows;
+  std::vector<double> dis(n, 0.0);   // 1 / sqrt(a_ii)
+#pragma omp parallel for
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] == i && A.v[k] > 0.0) dis[i] = 1.0 / std::sqrt(A.v[k]);
   double lmax = 0.0;
 #pragma omp parallel for reduction(max : lmax)
-  for (int64_t i = 0; i < A.n_rows; ++i) {
-    double s = 0.0, d = 0.0;
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      s += std::fabs(A.v[k]);
-      if (A.ci[k] == i) d = A.v[k];
-    }
-    if (d > 0.0) lmax = std::max(lmax, s / d);
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += std::fabs(A.v[k]) * dis[A.ci[k]];
+    lmax = std::max(lmax, s * dis[i]);
   }
   return lmax;
 }

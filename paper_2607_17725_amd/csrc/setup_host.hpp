@@ -54,7 +54,9 @@ HostBlocks galerkin_blocks(const HostCells &fine, const HostBlocks &kf, const in
 
 HostCSR transpose(const HostCSR &A);
 
-// max_i sum_j |a_ij| / a_ii (Gershgorin bound of D^-1 A).
+// max_i sum_j |a_ij| / sqrt(a_ii a_jj): Gershgorin bound of D^-1/2 A D^-1/2,
+// which has the spectrum of D^-1 A and stays bounded by the row length for
+// symmetric positive semi-definite A even where some a_ii are tiny.
 double gershgorin_scaled(const HostCSR &A);
 
 // Floating components of a symmetric matrix graph: connected components whose

@@ -149,7 +149,8 @@ def test_prolongation_reproduces_polynomials(fx, request):
     for t, P in enumerate(pb.P):
         Dc = _dof_values(pb, t + 1, q)
         Df = _dof_values(pb, t, q)
-        assert np.abs(P @ Dc - Df).max() < 1e-10 * max(np.abs(Df).max(), 1.0)
+        # coarse DOFs whose largest weight is below 1e-10 are dropped as unused
+        assert np.abs(P @ Dc - Df).max() < 1e-9 * max(np.abs(Df).max(), 1.0)
 
 
 def test_prolongation_trilinear_on_uncut_grid():

@@ -92,6 +92,7 @@ def main():
         print("bench.py: this build runs on one GPU; multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 
+    os.environ.setdefault("FVEM_VERBOSE", "1")   # setup progress lines on stderr
     import numpy as np
     import torch
     import synth

@@ -22,6 +22,7 @@
 #include "kernels.hpp"
 #include "grid.hpp"
 #include "setup_host.hpp"
+#include "progress.hpp"
 
 namespace fvem {
 
@@ -248,12 +249,16 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   // operators per level: A_0 from element blocks, A_{l+1} element-wise Galerkin
   std::vector<HostCSR> A(L), P(L);
   A[0] = assemble_blocks(h->n0, h->n0, c0, c0, ke);
+  progress("hierarchy: level 0 assembled, n=%lld nnz=%lld", static_cast<long long>(A[0].n_rows),
+           static_cast<long long>(A[0].rp.back()));
   HostBlocks kcur = std::move(ke);
   for (int l = 0; l + 1 < L; ++l) {
     const int64_t nf = g->levels[l].n_dof, nc = g->levels[l + 1].n_dof;
     P[l] = csr_of(g->levels[l].P, nf, nc, "prolongation");
     HostBlocks knext = galerkin_blocks(cells[l], kcur, g->levels[l].parent, cells[l + 1], P[l]);
     A[l + 1] = assemble_blocks(nc, nc, cells[l + 1], cells[l + 1], knext);
+    progress("hierarchy: Galerkin level %d, n=%lld nnz=%lld", l + 1, static_cast<long long>(nc),
+             static_cast<long long>(A[l + 1].rp.back()));
     kcur = std::move(knext);
   }
   { HostBlocks().val.swap(kcur.val); }
@@ -295,6 +300,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     h->BT = upload_csr(h, transpose(Bh), false, s);
   }
   h->comp0 = h->mem.upload(comp0, s);
+  progress("hierarchy: operators uploaded");
 
   // coarsest level: dense semi-definite factorisation and generalised inverse
   const HostCSR &Ac = A[L - 1];
@@ -331,6 +337,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     if (hflag) throw SetupError{FVEM_ERR_NOT_SPD, "coarsest operator is not positive semi-definite"};
+    progress("hierarchy: coarsest level factorised, n=%lld", static_cast<long long>(n));
     h->bc = h->mem.alloc<double>(n);
     h->xc = h->mem.alloc<double>(n);
   }

@@ -21,6 +21,7 @@
 //    neighbouring cells of the full (fluid + solid) tiling, with T-junction
 //    vertices inserted; coarse DOFs the prolongation never uses are dropped.
 #include "grid.hpp"
+#include "progress.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -1076,10 +1077,13 @@ struct BuilderImpl {
   // ------------------------------------------------------------------ driver
   void run() {
     build_forest();
+    progress("grid: %zu cut-cell trees", trees.size());
     levels.push_back(initial_level());
     make_tiles(levels[0]);
     conform(levels[0]);
     number_dofs(levels[0]);
+    progress("grid: level 0 has %lld cells and %lld DOFs", static_cast<long long>(levels[0].mesh.nc()),
+             static_cast<long long>(levels[0].nfree));
     int t = 0;
     while (true) {
       const int64_t n_here = levels.back().nfree;
@@ -1161,10 +1165,13 @@ struct BuilderImpl {
         for (int32_t &j : ci) j = remap[j];
         drop_unused(levels.back(), used);
       }
+      progress("grid: level %zu has %lld cells and %lld DOFs", levels.size() - 1,
+               static_cast<long long>(levels.back().mesh.nc()), static_cast<long long>(levels.back().nfree));
       out->P.push_back({std::move(rp), std::move(ci), std::move(va)});
       ++t;
     }
     emit();
+    progress("grid: element operators done");
   }
 
   void emit() {

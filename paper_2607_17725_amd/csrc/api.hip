@@ -71,9 +71,27 @@ struct DevCSR {
   DevCSRView<float> f() const { return {n, m, nnz, rp, ci, v32}; }
 };
 
+// Level operator in the sliced layout; one column array serves both value
+// precisions.  Host copies of the slice table and row lengths let the
+// operator be read back.
+struct DevSELL {
+  int64_t n = 0, m = 0, nnz = 0, nslices = 0, stored = 0;
+  int64_t *sp = nullptr;
+  int32_t *sl = nullptr;
+  int32_t *ci = nullptr;
+  double *v64 = nullptr;
+  float *v32 = nullptr;
+  std::vector<int64_t> hsp;
+  std::vector<int32_t> hsl, hrl;
+  DevSELLView<double> d() const { return {n, m, nslices, sp, sl, ci, v64}; }
+  DevSELLView<float> f() const { return {n, m, nslices, sp, sl, ci, v32}; }
+};
+
 struct Level {
   int64_t n = 0;
-  DevCSR A, P, R;
+  DevSELL A;
+  DevCSR P, R;
+  std::vector<int32_t> order;   // level order: order[internal] = caller's DOF index
   double *dinv64 = nullptr;
   float *dinv32 = nullptr;
   double lmax = 0;
@@ -91,6 +109,7 @@ struct fvem_hierarchy {
   std::vector<fvem::Level> lv;
   fvem::DevCSR B, BT;
   int64_t nvert = 0, n0 = 0;
+  int32_t *perm0 = nullptr, *iperm0 = nullptr;   // level-0 order and its inverse (device)
   int32_t *comp0 = nullptr;
   int ncomp0 = 0;
   // coarsest level
@@ -159,7 +178,35 @@ static DevCSR upload_csr(fvem_hierarchy *h, const HostCSR &A, bool f32, hipStrea
     d.v32 = h->mem.alloc<float>(d.nnz);
     cast_f64_f32(d.nnz, d.v64, d.v32, s);
   }
+  HIPCHECK(hipStreamSynchronize(s));   // the host arrays may be temporaries
   return d;
+}
+
+static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, hipStream_t s) {
+  HostSELL S = to_sell(A);
+  DevSELL d;
+  d.n = S.n;
+  d.m = S.m;
+  d.nnz = S.nnz;
+  d.nslices = S.nslices;
+  d.stored = S.sp.back();
+  d.sp = h->mem.upload(S.sp, s);
+  d.sl = h->mem.upload(S.sl, s);
+  d.ci = h->mem.upload(S.ci, s);
+  d.v64 = h->mem.upload(S.v, s);
+  d.v32 = h->mem.alloc<float>(d.stored);
+  cast_f64_f32(d.stored, d.v64, d.v32, s);
+  HIPCHECK(hipStreamSynchronize(s));   // the host arrays are freed on return
+  d.hsp = std::move(S.sp);
+  d.hsl = std::move(S.sl);
+  d.hrl = std::move(S.rl);
+  return d;
+}
+
+static std::vector<int32_t> inverse(const std::vector<int32_t> &order) {
+  std::vector<int32_t> inv(order.size());
+  for (size_t i = 0; i < order.size(); ++i) inv[order[i]] = static_cast<int32_t>(i);
+  return inv;
 }
 
 static void cheb_coefficients(Level &L, int deg, double lower) {
@@ -263,11 +310,31 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   }
   { HostBlocks().val.swap(kcur.val); }
 
+  // level order: rows sorted by length inside windows of 4096 (sliced
+  // storage pads each 64-row slice to its longest row); every level
+  // operator, transfer and per-DOF array is renumbered into it
+  constexpr int64_t ORDER_WINDOW = 4096;
+  std::vector<std::vector<int32_t>> inv(L);
+  for (int l = 0; l < L; ++l) {
+    h->lv[l].order = window_order(A[l], ORDER_WINDOW);
+    inv[l] = inverse(h->lv[l].order);
+    A[l] = permute(A[l], h->lv[l].order, &inv[l]);
+  }
+  for (int l = 0; l + 1 < L; ++l) P[l] = permute(P[l], h->lv[l].order, &inv[l + 1]);
+  if (g->n_vert > 0) Bh = permute(Bh, h->lv[0].order, nullptr);
+  {
+    std::vector<int32_t> c(h->n0);
+    for (int64_t i = 0; i < h->n0; ++i) c[i] = comp0[h->lv[0].order[i]];
+    comp0.swap(c);
+  }
+  h->perm0 = h->mem.upload(h->lv[0].order, s);
+  h->iperm0 = h->mem.upload(inv[0], s);
+
   // upload
   for (int l = 0; l < L; ++l) {
     Level &V = h->lv[l];
     V.n = A[l].n_rows;
-    V.A = upload_csr(h, A[l], true, s);
+    V.A = upload_sell(h, A[l], s);
     std::vector<double> dinv(V.n);
     for (int64_t i = 0; i < V.n; ++i) {
       double d = 0.0;
@@ -294,6 +361,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     V.xb32 = h->mem.alloc<float>(V.n);
     V.d32 = h->mem.alloc<float>(V.n);
     V.r32 = h->mem.alloc<float>(V.n);
+    if (l + 1 < L) A[l] = HostCSR();   // the coarsest stays for the dense factorisation
   }
   if (g->n_vert > 0) {
     h->B = upload_csr(h, Bh, false, s);
@@ -325,8 +393,13 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     double *X = tmp.alloc<double>(n * n);
     int *flag = tmp.alloc<int>(1);
     HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), s));
-    const Level &C = h->lv[L - 1];
-    dense_from_csr(n, C.A.rp, C.A.ci, C.A.v64, D, s);
+    int64_t *crp = tmp.alloc<int64_t>(n + 1);
+    int32_t *cci = tmp.alloc<int32_t>(Ac.nnz());
+    double *cv = tmp.alloc<double>(Ac.nnz());
+    HIPCHECK(hipMemcpyAsync(crp, Ac.rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(cci, Ac.ci.data(), sizeof(int32_t) * Ac.nnz(), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(cv, Ac.v.data(), sizeof(double) * Ac.nnz(), hipMemcpyHostToDevice, s));
+    dense_from_csr(n, crp, cci, cv, D, s);
     add_diagonal(n, D, ds, s);
     potrf_semidefinite(D, n, dg, rcond, flag, s);
     trinv_semidefinite(D, X, n, s);
@@ -368,7 +441,7 @@ template <> struct Vec<double> {
   static double *d(Level &L) { return L.d64; }
   static double *r(Level &L) { return L.r64; }
   static const double *dinv(Level &L) { return L.dinv64; }
-  static DevCSRView<double> A(Level &L) { return L.A.d(); }
+  static DevSELLView<double> A(Level &L) { return L.A.d(); }
   static DevCSRView<double> P(Level &L) { return L.P.d(); }
   static DevCSRView<double> R(Level &L) { return L.R.d(); }
 };
@@ -379,7 +452,7 @@ template <> struct Vec<float> {
   static float *d(Level &L) { return L.d32; }
   static float *r(Level &L) { return L.r32; }
   static const float *dinv(Level &L) { return L.dinv32; }
-  static DevCSRView<float> A(Level &L) { return L.A.f(); }
+  static DevSELLView<float> A(Level &L) { return L.A.f(); }
   static DevCSRView<float> P(Level &L) { return L.P.f(); }
   static DevCSRView<float> R(Level &L) { return L.R.f(); }
 };
@@ -481,7 +554,7 @@ static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const
   const int maxit = (so && so->maxit > 0) ? so->maxit : 500;
   const bool mixed = so && so->precision == FVEM_PREC_MIXED;
   const int m = (so && so->replace_every > 0) ? so->replace_every : 10;
-  const DevCSRView<double> K = h->lv[0].A.d();
+  const DevSELLView<double> K = h->lv[0].A.d();
   HIPCHECK(hipMemcpyAsync(h->b, bin, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   if (h->ncomp0) project_components(n, h->b, h->comp0, h->ncomp0, h->partial, h->mean, s);
   double d[3];
@@ -555,21 +628,20 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   HIPCHECK(hipEventRecord(e0, s));
+  // caller's DOF order <-> level order at the boundary of the solve
+  const int64_t n = h->n0;
   fvem_status stt;
   if (!adjoint) {
-    const double *rhs = in;
-    if (velocity) {
-      spmv<double>(h->B.d(), in, h->q, s);
-      rhs = h->q;
-    }
-    stt = pcg(h, rhs, out, so, st, s);
+    const double *rhs = h->q;
+    if (velocity) spmv<double>(h->B.d(), in, h->q, s);
+    else gather(n, h->perm0, in, h->q, s);
+    stt = pcg(h, rhs, h->lam, so, st, s);
+    gather(n, h->iperm0, h->lam, out, s);
   } else {
-    if (velocity) {
-      stt = pcg(h, in, h->lam, so, st, s);
-      spmv<double>(h->BT.d(), h->lam, out, s);
-    } else {
-      stt = pcg(h, in, out, so, st, s);
-    }
+    gather(n, h->perm0, in, h->q, s);
+    stt = pcg(h, h->q, h->lam, so, st, s);
+    if (velocity) spmv<double>(h->BT.d(), h->lam, out, s);
+    else gather(n, h->iperm0, h->lam, out, s);
   }
   HIPCHECK(hipEventRecord(e1, s));
   HIPCHECK(hipEventSynchronize(e1));
@@ -689,30 +761,38 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
   return guard([&] {
     const int64_t n = h->n0;
     switch (op) {
-      case FVEM_OP_K: spmv<double>(h->lv[0].A.d(), x, y, s); break;
+      case FVEM_OP_K:
+        gather(n, h->perm0, x, h->p, s);
+        spmv<double>(h->lv[0].A.d(), h->p, h->q, s);
+        gather(n, h->iperm0, h->q, y, s);
+        break;
       case FVEM_OP_B:
         check(h->nvert > 0, "no divergence operator");
-        spmv<double>(h->B.d(), x, y, s);
+        spmv<double>(h->B.d(), x, h->q, s);
+        gather(n, h->iperm0, h->q, y, s);
         break;
       case FVEM_OP_BT:
         check(h->nvert > 0, "no divergence operator");
-        spmv<double>(h->BT.d(), x, y, s);
+        gather(n, h->perm0, x, h->p, s);
+        spmv<double>(h->BT.d(), h->p, y, s);
         break;
       case FVEM_OP_VCYCLE:
       case FVEM_OP_VCYCLE32: {
-        HIPCHECK(hipMemcpyAsync(h->r, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        gather(n, h->perm0, x, h->r, s);
         double nr = 1.0;
         if (op == FVEM_OP_VCYCLE32) {
           double d[1];
           dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
           nr = std::sqrt(d[0]);
         }
-        precondition(h, h->r, y, op == FVEM_OP_VCYCLE32, nr, s);
+        precondition(h, h->r, h->z, op == FVEM_OP_VCYCLE32, nr, s);
+        gather(n, h->iperm0, h->z, y, s);
         break;
       }
       case FVEM_OP_PROJECT:
-        HIPCHECK(hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        if (h->ncomp0) project_components(n, y, h->comp0, h->ncomp0, h->partial, h->mean, s);
+        gather(n, h->perm0, x, h->z, s);
+        if (h->ncomp0) project_components(n, h->z, h->comp0, h->ncomp0, h->partial, h->mean, s);
+        gather(n, h->iperm0, h->z, y, s);
         break;
       default: throw SetupError{FVEM_ERR_INVALID, "unknown operator"};
     }
@@ -728,12 +808,28 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
     return FVEM_ERR_INVALID;
   }
   return guard([&] {
-    const DevCSR &A = h->lv[level].A;
+    const DevSELL &A = h->lv[level].A;
     if (n_rows) *n_rows = A.n;
     if (nnz) *nnz = A.nnz;
-    if (row_ptr) HIPCHECK(hipMemcpy(row_ptr, A.rp, sizeof(int64_t) * (A.n + 1), hipMemcpyDeviceToHost));
-    if (col) HIPCHECK(hipMemcpy(col, A.ci, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost));
-    if (val) HIPCHECK(hipMemcpy(val, A.v64, sizeof(double) * A.nnz, hipMemcpyDeviceToHost));
+    if (!row_ptr && !col && !val) return FVEM_OK;
+    // read back the sliced operator and return it in the caller's order
+    HostSELL S;
+    S.n = A.n;
+    S.m = A.m;
+    S.nnz = A.nnz;
+    S.nslices = A.nslices;
+    S.sp = A.hsp;
+    S.sl = A.hsl;
+    S.rl = A.hrl;
+    S.ci.resize(A.stored);
+    S.v.resize(A.stored);
+    HIPCHECK(hipMemcpy(S.ci.data(), A.ci, sizeof(int32_t) * A.stored, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(S.v.data(), A.v64, sizeof(double) * A.stored, hipMemcpyDeviceToHost));
+    const std::vector<int32_t> &order = h->lv[level].order;
+    const HostCSR C = permute(from_sell(S), inverse(order), &order);
+    if (row_ptr) std::copy(C.rp.begin(), C.rp.end(), row_ptr);
+    if (col) std::copy(C.ci.begin(), C.ci.end(), col);
+    if (val) std::copy(C.v.begin(), C.v.end(), val);
     return FVEM_OK;
   });
 }

@@ -96,6 +96,89 @@ static void launch_spmv(const DevCSRView<VT> &A, const XT *x, Epi epi, hipStream
   }
 }
 
+// Sliced ELLPACK: one wavefront per 64-row slice, one lane per row, so the
+// value and column loads of a step j are one contiguous 256-byte (FP32) or
+// 512-byte (FP64) read per wavefront.  Rows inside each window of the level
+// order are sorted by length at setup, so a slice's rows have (nearly) equal
+// length and padding is a few percent.  The matrix is streamed once per
+// launch with non-temporal loads, leaving the caches to the gathered x.
+// Workgroups are dispatched round-robin over the 8 XCDs; remapping the
+// workgroup id gives each XCD a contiguous range of slices, so x entries
+// shared by neighbouring slices are reused in that XCD's L2.
+
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7;
+  const int64_t xcd = b & 7, idx = b >> 3;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+constexpr int SELL_UNROLL = 8;
+
+template <typename VT, typename XT, class Epi>
+__global__ __launch_bounds__(256) void sell_kernel(int64_t n, int64_t nslices, const int64_t *__restrict__ sp,
+                                                   const int32_t *__restrict__ sl, const int32_t *__restrict__ ci,
+                                                   const VT *__restrict__ val, const XT *__restrict__ x, Epi epi) {
+  const int64_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t slice = blk * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;
+  using AT = typename Epi::acc_t;
+  const int64_t base = sp[slice] + lane;
+  const int len = sl[slice];
+  const int32_t *cp = ci + base;
+  const VT *vp = val + base;
+  AT acc = 0;
+  int j = 0;
+  for (; j + SELL_UNROLL <= len; j += SELL_UNROLL) {
+    int32_t c[SELL_UNROLL];
+    VT v[SELL_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SELL_UNROLL; ++u) {
+      c[u] = __builtin_nontemporal_load(cp + static_cast<int64_t>(j + u) * 64);
+      v[u] = __builtin_nontemporal_load(vp + static_cast<int64_t>(j + u) * 64);
+    }
+#pragma unroll
+    for (int u = 0; u < SELL_UNROLL; ++u) acc += static_cast<AT>(v[u]) * static_cast<AT>(x[c[u]]);
+  }
+  for (; j < len; ++j) {
+    const int32_t c = __builtin_nontemporal_load(cp + static_cast<int64_t>(j) * 64);
+    const VT v = __builtin_nontemporal_load(vp + static_cast<int64_t>(j) * 64);
+    acc += static_cast<AT>(v) * static_cast<AT>(x[c]);
+  }
+  const int64_t row = slice * 64 + lane;
+  if (row < n) epi(row, acc);
+}
+
+template <typename VT, typename XT, class Epi>
+static void launch_sell(const DevSELLView<VT> &A, const XT *x, Epi epi, hipStream_t s) {
+  if (A.nslices == 0) return;
+  const dim3 grid(static_cast<unsigned>((A.nslices + 3) / 4));
+  sell_kernel<VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.nslices, A.sp, A.sl, A.ci, A.v, x, epi);
+}
+
+template <typename T>
+void spmv(const DevSELLView<T> &A, const T *x, T *y, hipStream_t s) {
+  launch_sell(A, x, EpiStore<T>{y}, s);
+}
+template <typename T>
+void residual(const DevSELLView<T> &A, const T *x, const T *b, T *r, hipStream_t s) {
+  launch_sell(A, x, EpiResidual<T>{b, r}, s);
+}
+template <typename T>
+void cheb_step(const DevSELLView<T> &A, const T *b, const T *dinv, const T *xin, T *d, T *xout, T ca, T cb,
+               hipStream_t s) {
+  launch_sell(A, xin, EpiCheb<T>{b, dinv, xin, d, xout, ca, cb}, s);
+}
+template void spmv<double>(const DevSELLView<double> &, const double *, double *, hipStream_t);
+template void spmv<float>(const DevSELLView<float> &, const float *, float *, hipStream_t);
+template void residual<double>(const DevSELLView<double> &, const double *, const double *, double *,
+                               hipStream_t);
+template void residual<float>(const DevSELLView<float> &, const float *, const float *, float *, hipStream_t);
+template void cheb_step<double>(const DevSELLView<double> &, const double *, const double *, const double *,
+                                double *, double *, double, double, hipStream_t);
+template void cheb_step<float>(const DevSELLView<float> &, const float *, const float *, const float *, float *,
+                               float *, float, float, hipStream_t);
+
 template <typename T>
 void spmv(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s) {
   launch_spmv(A, x, EpiStore<T>{y}, s);
@@ -152,6 +235,16 @@ void cheb_first(int64_t n, const T *b, const T *dinv, T *d, T *x, T cb, hipStrea
 template void cheb_first<double>(int64_t, const double *, const double *, double *, double *, double,
                                  hipStream_t);
 template void cheb_first<float>(int64_t, const float *, const float *, float *, float *, float, hipStream_t);
+
+__global__ void gather_kernel(int64_t n, const int32_t *idx, const double *x, double *y) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = x[idx[i]];
+}
+
+void gather(int64_t n, const int32_t *idx, const double *x, double *y, hipStream_t s) {
+  if (n) gather_kernel<<<vgrid(n), 256, 0, s>>>(n, idx, x, y);
+}
 
 __global__ void cast_scale_kernel_df(int64_t n, const double *a, float *b, double s) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -275,33 +368,44 @@ void dots(int64_t n, int ndot, const double *a0, const double *b0, const double 
   }
 }
 
-// Zero mean per pure-Neumann component (up to MAX_COMP components per pass).
+// Zero mean per pure-Neumann component (COMP_CHUNK components per pass).
+// Per-component sums and counts of one block's contiguous chunk: every
+// thread accumulates its strided elements into its own LDS slot per
+// component, then the slots are combined by a fixed-order tree, so the
+// result is independent of scheduling.
+constexpr int COMP_CHUNK = 16;
+
 __global__ __launch_bounds__(256) void comp_partial_kernel(int64_t n, const double *v, const int32_t *comp,
                                                            int c0, int nc, double *partial) {
-  __shared__ double s_sum[MAX_COMP];
-  __shared__ double s_cnt[MAX_COMP];
-  for (int j = threadIdx.x; j < nc; j += 256) {
-    s_sum[j] = 0.0;
-    s_cnt[j] = 0.0;
+  __shared__ double s_sum[COMP_CHUNK][256];
+  __shared__ double s_cnt[COMP_CHUNK][256];
+  const int t = threadIdx.x;
+  for (int j = 0; j < nc; ++j) {
+    s_sum[j][t] = 0.0;
+    s_cnt[j][t] = 0.0;
   }
-  __syncthreads();
-  // sequential per block for determinism: each thread reduces a contiguous chunk
   const int64_t per_block = (n + REDUCE_BLOCKS - 1) / REDUCE_BLOCKS;
   const int64_t lo = blockIdx.x * per_block;
   const int64_t hi = lo + per_block < n ? lo + per_block : n;
-  if (threadIdx.x == 0) {
-    for (int64_t i = lo; i < hi; ++i) {
-      const int c = comp[i] - c0;
-      if (c >= 0 && c < nc) {
-        s_sum[c] += v[i];
-        s_cnt[c] += 1.0;
-      }
+  for (int64_t i = lo + t; i < hi; i += 256) {
+    const int c = comp[i] - c0;
+    if (c >= 0 && c < nc) {
+      s_sum[c][t] += v[i];
+      s_cnt[c][t] += 1.0;
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < nc; j += 256) {
-    partial[(2 * j) * REDUCE_BLOCKS + blockIdx.x] = s_sum[j];
-    partial[(2 * j + 1) * REDUCE_BLOCKS + blockIdx.x] = s_cnt[j];
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o)
+      for (int j = 0; j < nc; ++j) {
+        s_sum[j][t] += s_sum[j][t + o];
+        s_cnt[j][t] += s_cnt[j][t + o];
+      }
+    __syncthreads();
+  }
+  if (t < nc) {
+    partial[(2 * t) * REDUCE_BLOCKS + blockIdx.x] = s_sum[t][0];
+    partial[(2 * t + 1) * REDUCE_BLOCKS + blockIdx.x] = s_cnt[t][0];
   }
 }
 
@@ -336,8 +440,8 @@ __global__ void comp_sub_kernel(int64_t n, double *v, const int32_t *comp, int c
 
 void project_components(int64_t n, double *v, const int32_t *comp, int n_comp, double *partial, double *mean,
                         hipStream_t s) {
-  for (int c0 = 0; c0 < n_comp; c0 += MAX_COMP) {
-    const int nc = n_comp - c0 < MAX_COMP ? n_comp - c0 : MAX_COMP;
+  for (int c0 = 0; c0 < n_comp; c0 += COMP_CHUNK) {
+    const int nc = n_comp - c0 < COMP_CHUNK ? n_comp - c0 : COMP_CHUNK;
     comp_partial_kernel<<<REDUCE_BLOCKS, 256, 0, s>>>(n, v, comp, c0, nc, partial);
     comp_final_kernel<<<nc, 256, 0, s>>>(nc, partial, mean);
     comp_sub_kernel<<<vgrid(n), 256, 0, s>>>(n, v, comp, c0, nc, mean);

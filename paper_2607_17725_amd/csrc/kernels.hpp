@@ -17,7 +17,27 @@ struct DevCSRView {
   const T *v = nullptr;
 };
 
-// SpMV family (vector CSR with fused epilogues)
+// Sliced ELLPACK with 64-row slices (one wavefront lane per row).  Slice s
+// holds rows [64 s, 64 s + 64); its entries are stored column-major, entry j
+// of lane r at sp[s] + 64 j + r, for j < sl[s] (the longest row of the
+// slice).  Shorter rows are padded with value 0 and a valid column.
+template <typename T>
+struct DevSELLView {
+  int64_t n = 0, m = 0, nslices = 0;
+  const int64_t *sp = nullptr;
+  const int32_t *sl = nullptr;
+  const int32_t *ci = nullptr;
+  const T *v = nullptr;
+};
+
+// SpMV family on the sliced layout (level operators; fused epilogues)
+template <typename T> void spmv(const DevSELLView<T> &A, const T *x, T *y, hipStream_t s);
+template <typename T> void residual(const DevSELLView<T> &A, const T *x, const T *b, T *r, hipStream_t s);
+template <typename T>
+void cheb_step(const DevSELLView<T> &A, const T *b, const T *dinv, const T *xin, T *d, T *xout, T ca, T cb,
+               hipStream_t s);
+
+// SpMV family (vector CSR with fused epilogues; transfers and divergence)
 template <typename T> void spmv(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s);
 template <typename T> void residual(const DevCSRView<T> &A, const T *x, const T *b, T *r, hipStream_t s);
 template <typename T> void spmv_add(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s);
@@ -27,6 +47,7 @@ void cheb_step(const DevCSRView<T> &A, const T *b, const T *dinv, const T *xin, 
 template <typename T> void cheb_first(int64_t n, const T *b, const T *dinv, T *d, T *x, T cb, hipStream_t s);
 
 // vectors
+void gather(int64_t n, const int32_t *idx, const double *x, double *y, hipStream_t s);   // y[i] = x[idx[i]]
 void cast_scale(int64_t n, const double *a, float *b, double s, hipStream_t st);
 void cast_scale(int64_t n, const float *a, double *b, double s, hipStream_t st);
 void cast_f64_f32(int64_t n, const double *a, float *b, hipStream_t s);

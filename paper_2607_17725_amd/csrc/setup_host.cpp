@@ -176,6 +176,96 @@ HostCSR transpose(const HostCSR &A) {
   return T;
 }
 
+std::vector<int32_t> window_order(const HostCSR &A, int64_t w) {
+  const int64_t n = A.n_rows;
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < (n + w - 1) / w; ++s) {
+    auto b = order.begin() + s * w, e = order.begin() + std::min(n, (s + 1) * w);
+    std::stable_sort(b, e, [&](int32_t a, int32_t c) {
+      return A.rp[a + 1] - A.rp[a] > A.rp[c + 1] - A.rp[c];
+    });
+  }
+  return order;
+}
+
+HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::vector<int32_t> *col_map) {
+  HostCSR B;
+  B.n_rows = A.n_rows;
+  B.n_cols = A.n_cols;
+  B.rp.assign(B.n_rows + 1, 0);
+  for (int64_t r = 0; r < B.n_rows; ++r) B.rp[r + 1] = B.rp[r] + (A.rp[order[r] + 1] - A.rp[order[r]]);
+  B.ci.resize(A.nnz());
+  B.v.resize(A.nnz());
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t r = 0; r < B.n_rows; ++r) {
+    const int64_t o = order[r], len = A.rp[o + 1] - A.rp[o];
+    std::vector<std::pair<int32_t, double>> e(len);
+    for (int64_t q = 0; q < len; ++q) {
+      const int32_t c = A.ci[A.rp[o] + q];
+      e[q] = {col_map ? (*col_map)[c] : c, A.v[A.rp[o] + q]};
+    }
+    std::sort(e.begin(), e.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (int64_t q = 0; q < len; ++q) {
+      B.ci[B.rp[r] + q] = e[q].first;
+      B.v[B.rp[r] + q] = e[q].second;
+    }
+  }
+  return B;
+}
+
+HostSELL to_sell(const HostCSR &A) {
+  HostSELL S;
+  S.n = A.n_rows;
+  S.m = A.n_cols;
+  S.nnz = A.nnz();
+  S.nslices = (S.n + 63) / 64;
+  S.sl.assign(S.nslices, 0);
+  S.rl.assign(S.n, 0);
+  S.sp.assign(S.nslices + 1, 0);
+  for (int64_t i = 0; i < S.n; ++i) {
+    S.rl[i] = static_cast<int32_t>(A.rp[i + 1] - A.rp[i]);
+    S.sl[i / 64] = std::max(S.sl[i / 64], S.rl[i]);
+  }
+  for (int64_t s = 0; s < S.nslices; ++s) S.sp[s + 1] = S.sp[s] + 64 * static_cast<int64_t>(S.sl[s]);
+  S.ci.assign(S.sp.back(), 0);
+  S.v.assign(S.sp.back(), 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < S.nslices; ++s)
+    for (int r = 0; r < 64; ++r) {
+      const int64_t i = s * 64 + r;
+      const int32_t pad = static_cast<int32_t>(std::min<int64_t>(std::min(i, S.n - 1), S.m - 1));
+      for (int j = 0; j < S.sl[s]; ++j) {
+        const int64_t dst = S.sp[s] + 64 * static_cast<int64_t>(j) + r;
+        if (i < S.n && j < S.rl[i]) {
+          S.ci[dst] = A.ci[A.rp[i] + j];
+          S.v[dst] = A.v[A.rp[i] + j];
+        } else {
+          S.ci[dst] = pad < 0 ? 0 : pad;
+        }
+      }
+    }
+  return S;
+}
+
+HostCSR from_sell(const HostSELL &S) {
+  HostCSR A;
+  A.n_rows = S.n;
+  A.n_cols = S.m;
+  A.rp.assign(S.n + 1, 0);
+  for (int64_t i = 0; i < S.n; ++i) A.rp[i + 1] = A.rp[i] + S.rl[i];
+  A.ci.resize(A.rp.back());
+  A.v.resize(A.rp.back());
+  for (int64_t i = 0; i < S.n; ++i)
+    for (int j = 0; j < S.rl[i]; ++j) {
+      const int64_t src = S.sp[i / 64] + 64 * static_cast<int64_t>(j) + i % 64;
+      A.ci[A.rp[i] + j] = S.ci[src];
+      A.v[A.rp[i] + j] = S.v[src];
+    }
+  return A;
+}
+
 double gershgorin_scaled(const HostCSR &A) {
   const int64_t n = A.n_rows;
   std::vector<double> dis(n, 0.0);   // 1 / sqrt(a_ii)

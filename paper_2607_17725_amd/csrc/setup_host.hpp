@@ -54,6 +54,27 @@ HostBlocks galerkin_blocks(const HostCells &fine, const HostBlocks &kf, const in
 
 HostCSR transpose(const HostCSR &A);
 
+// Level order of the sliced storage: inside each window of w consecutive
+// rows, rows by decreasing length (stable).  Returns order[new] = old.
+std::vector<int32_t> window_order(const HostCSR &A, int64_t w);
+
+// B = rows order[r] of A with columns renamed by col_map (old -> new; null
+// keeps them), columns sorted ascending within each row.
+HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::vector<int32_t> *col_map);
+
+// Sliced ELLPACK (64-row slices, column-major inside a slice); padding has
+// value 0 and column min(row, n_cols - 1).
+struct HostSELL {
+  int64_t n = 0, m = 0, nnz = 0, nslices = 0;
+  std::vector<int64_t> sp;   // nslices + 1, in entries
+  std::vector<int32_t> sl;   // longest row per slice
+  std::vector<int32_t> rl;   // row lengths
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+};
+HostSELL to_sell(const HostCSR &A);
+HostCSR from_sell(const HostSELL &S);
+
 // max_i sum_j |a_ij| / sqrt(a_ii a_jj): Gershgorin bound of D^-1/2 A D^-1/2,
 // which has the spectrum of D^-1 A and stays bounded by the row length for
 // symmetric positive semi-definite A even where some a_ii are tiny.

@@ -1,0 +1,244 @@
+// Checks of the library's host-side setup routines (sliced storage, level
+// order, permutation, transpose, block assembly, element-wise Galerkin
+// product, scaled Gershgorin bound) against dense brute force on small
+// random inputs.  Built with g++ by tests/test_host_setup.py; prints one line
+// per check and exits non-zero on the first failure.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "../paper_2607_17725_amd/csrc/setup_host.hpp"
+
+using namespace fvem;
+
+static int failures = 0;
+
+static void expect(bool ok, const char *what) {
+  std::printf("%s %s\n", ok ? "ok  " : "FAIL", what);
+  if (!ok) ++failures;
+}
+
+static std::vector<double> dense(const HostCSR &A) {
+  std::vector<double> D(A.n_rows * A.n_cols, 0.0);
+  for (int64_t i = 0; i < A.n_rows; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) D[i * A.n_cols + A.ci[k]] += A.v[k];
+  return D;
+}
+
+static HostCSR random_csr(std::mt19937 &g, int64_t n, int64_t m, int maxlen) {
+  std::uniform_int_distribution<int> len(0, maxlen), col(0, static_cast<int>(m - 1));
+  std::normal_distribution<double> val;
+  HostCSR A;
+  A.n_rows = n;
+  A.n_cols = m;
+  A.rp.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    std::vector<int> c;
+    const int l = len(g);
+    for (int q = 0; q < l; ++q) {
+      const int j = col(g);
+      bool dup = false;
+      for (int x : c) dup = dup || x == j;
+      if (!dup) c.push_back(j);
+    }
+    for (int j : c) {
+      A.ci.push_back(j);
+      A.v.push_back(val(g));
+    }
+    A.rp[i + 1] = static_cast<int64_t>(A.ci.size());
+  }
+  return A;
+}
+
+static double maxdiff(const std::vector<double> &a, const std::vector<double> &b) {
+  double d = a.size() == b.size() ? 0.0 : INFINITY;
+  for (size_t i = 0; i < a.size() && i < b.size(); ++i) d = std::max(d, std::fabs(a[i] - b[i]));
+  return d;
+}
+
+int main() {
+  std::mt19937 g(7);
+  // sliced storage round trip, ragged last slice and empty rows
+  for (int64_t n : {1, 63, 64, 65, 200, 1000}) {
+    HostCSR A = random_csr(g, n, n + 3, 90);
+    HostSELL S = to_sell(A);
+    bool ok = S.nslices == (n + 63) / 64 && S.sp.back() % 64 == 0;
+    for (int64_t s = 0; s < S.nslices; ++s) {
+      int mx = 0;
+      for (int64_t i = s * 64; i < std::min(n, s * 64 + 64); ++i) mx = std::max<int>(mx, static_cast<int>(A.rp[i + 1] - A.rp[i]));
+      ok = ok && S.sl[s] == mx;
+    }
+    for (int32_t c : S.ci) ok = ok && c >= 0 && c < A.n_cols;
+    // padding contributes zero: a dense product through the slices equals A x
+    std::vector<double> x(A.n_cols), y(n, 0.0);
+    for (auto &v : x) v = std::normal_distribution<double>()(g);
+    for (int64_t s = 0; s < S.nslices; ++s)
+      for (int r = 0; r < 64; ++r) {
+        const int64_t i = s * 64 + r;
+        if (i >= n) continue;
+        for (int j = 0; j < S.sl[s]; ++j) y[i] += S.v[S.sp[s] + 64 * j + r] * x[S.ci[S.sp[s] + 64 * j + r]];
+      }
+    std::vector<double> yr(n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) yr[i] += A.v[k] * x[A.ci[k]];
+    ok = ok && maxdiff(y, yr) < 1e-12;
+    const HostCSR B = from_sell(S);
+    ok = ok && B.rp == A.rp && B.ci == A.ci && B.v == A.v;
+    char msg[96];
+    std::snprintf(msg, sizeof msg, "sliced storage round trip, n=%lld", static_cast<long long>(n));
+    expect(ok, msg);
+  }
+  // level order: a permutation, sorted by decreasing length inside windows, stable
+  {
+    HostCSR A = random_csr(g, 1000, 1000, 40);
+    const int64_t w = 128;
+    std::vector<int32_t> o = window_order(A, w);
+    std::vector<int> seen(1000, 0);
+    bool ok = o.size() == 1000;
+    for (int32_t i : o) ok = ok && i >= 0 && i < 1000 && !seen[i]++;
+    for (int64_t r = 0; r + 1 < 1000; ++r) {
+      if ((r + 1) % w == 0) continue;
+      const int64_t la = A.rp[o[r] + 1] - A.rp[o[r]], lb = A.rp[o[r + 1] + 1] - A.rp[o[r + 1]];
+      ok = ok && (la > lb || (la == lb && o[r] < o[r + 1]));
+      ok = ok && o[r] / w == r / w;
+    }
+    expect(ok, "window order");
+    // symmetric renumbering: B = Q A Q^T with columns sorted per row
+    std::vector<int32_t> inv(1000);
+    for (int i = 0; i < 1000; ++i) inv[o[i]] = i;
+    HostCSR B = permute(A, o, &inv);
+    const std::vector<double> DA = dense(A), DB = dense(B);
+    bool same = true, sorted = true;
+    for (int64_t r = 0; r < 1000; ++r)
+      for (int64_t c = 0; c < 1000; ++c) same = same && DB[r * 1000 + c] == DA[o[r] * 1000 + o[c]];
+    for (int64_t r = 0; r < 1000; ++r)
+      for (int64_t k = B.rp[r]; k + 1 < B.rp[r + 1]; ++k) sorted = sorted && B.ci[k] < B.ci[k + 1];
+    expect(same && sorted, "symmetric renumbering");
+    HostCSR C = permute(B, inv, &o);
+    expect(dense(C) == DA, "renumbering inverts");
+  }
+  // transpose
+  {
+    HostCSR A = random_csr(g, 300, 170, 30);
+    HostCSR T = transpose(A);
+    const std::vector<double> DA = dense(A), DT = dense(T);
+    bool ok = T.n_rows == 170 && T.n_cols == 300;
+    for (int64_t i = 0; i < 300; ++i)
+      for (int64_t j = 0; j < 170; ++j) ok = ok && DA[i * 170 + j] == DT[j * 300 + i];
+    expect(ok, "transpose");
+  }
+  // block assembly and element-wise Galerkin product against dense sums
+  {
+    const int nf = 40, nc = 12, ncell_f = 18, ncell_c = 4, mf = 6, mc = 5;
+    std::uniform_int_distribution<int> df(-1, nf - 1), dc(0, nc - 1);
+    HostCells F, Cc;
+    F.n_cells = ncell_f;
+    Cc.n_cells = ncell_c;
+    F.ptr.push_back(0);
+    Cc.ptr.push_back(0);
+    std::vector<int32_t> parent(ncell_f);
+    for (int c = 0; c < ncell_c; ++c) {
+      std::vector<int> d;
+      while (static_cast<int>(d.size()) < mc) {
+        int j = dc(g);
+        bool dup = false;
+        for (int x : d) dup = dup || x == j;
+        if (!dup) d.push_back(j);
+      }
+      for (int j : d) Cc.dof.push_back(j);
+      Cc.ptr.push_back(static_cast<int64_t>(Cc.dof.size()));
+    }
+    for (int c = 0; c < ncell_f; ++c) {
+      std::vector<int> d;
+      while (static_cast<int>(d.size()) < mf) {
+        int j = df(g);
+        bool dup = false;
+        for (int x : d) dup = dup || (x == j && j >= 0);
+        if (!dup) d.push_back(j);
+      }
+      for (int j : d) F.dof.push_back(j);
+      F.ptr.push_back(static_cast<int64_t>(F.dof.size()));
+      parent[c] = c % ncell_c;
+    }
+    HostBlocks K;
+    K.off.resize(ncell_f);
+    for (int c = 0; c < ncell_f; ++c) {
+      K.off[c] = static_cast<int64_t>(K.val.size());
+      std::vector<double> M(mf * mf);
+      for (auto &v : M) v = std::normal_distribution<double>()(g);
+      for (int a = 0; a < mf; ++a)
+        for (int b = 0; b < mf; ++b) K.val.push_back(M[a * mf + b] + M[b * mf + a]);
+    }
+    HostCSR A = assemble_blocks(nf, nf, F, F, K);
+    std::vector<double> DA(nf * nf, 0.0);
+    for (int c = 0; c < ncell_f; ++c)
+      for (int a = 0; a < mf; ++a)
+        for (int b = 0; b < mf; ++b) {
+          const int i = F.dof[F.ptr[c] + a], j = F.dof[F.ptr[c] + b];
+          if (i >= 0 && j >= 0) DA[i * nf + j] += K.val[K.off[c] + a * mf + b];
+        }
+    expect(maxdiff(dense(A), DA) < 1e-12, "block assembly");
+    // a prolongation whose rows only reach the coarse DOFs of every parent
+    // of the cells holding the fine DOF
+    std::vector<std::vector<int>> allowed(nf);
+    for (int c = 0; c < ncell_f; ++c)
+      for (int a = 0; a < mf; ++a) {
+        const int i = F.dof[F.ptr[c] + a];
+        if (i < 0) continue;
+        std::vector<int> here(Cc.dof.begin() + Cc.ptr[parent[c]], Cc.dof.begin() + Cc.ptr[parent[c] + 1]);
+        if (allowed[i].empty()) {
+          allowed[i] = here;
+          allowed[i].push_back(-2);   // marks "initialised"
+        } else {
+          std::vector<int> keep{-2};
+          for (int j : allowed[i])
+            for (int q : here)
+              if (j == q) keep.push_back(j);
+          allowed[i] = keep;
+        }
+      }
+    HostCSR P;
+    P.n_rows = nf;
+    P.n_cols = nc;
+    P.rp.assign(nf + 1, 0);
+    for (int i = 0; i < nf; ++i) {
+      for (int j : allowed[i])
+        if (j >= 0 && std::uniform_real_distribution<double>()(g) < 0.7) {
+          P.ci.push_back(j);
+          P.v.push_back(std::normal_distribution<double>()(g));
+        }
+      P.rp[i + 1] = static_cast<int64_t>(P.ci.size());
+    }
+    HostBlocks Kc = galerkin_blocks(F, K, parent.data(), Cc, P);
+    HostCSR Ac = assemble_blocks(nc, nc, Cc, Cc, Kc);
+    const std::vector<double> DP = dense(P);
+    std::vector<double> R(nc * nc, 0.0);
+    for (int a = 0; a < nc; ++a)
+      for (int b = 0; b < nc; ++b)
+        for (int i = 0; i < nf; ++i)
+          for (int j = 0; j < nf; ++j) R[a * nc + b] += DP[i * nc + a] * DA[i * nf + j] * DP[j * nc + b];
+    double scale = 0.0;
+    for (double v : R) scale = std::max(scale, std::fabs(v));
+    expect(maxdiff(dense(Ac), R) < 1e-12 * scale, "element-wise Galerkin product equals P^T A P");
+  }
+  // scaled Gershgorin bound of D^-1/2 A D^-1/2 for the 1D Laplacian: 2
+  {
+    const int n = 50;
+    HostCSR A;
+    A.n_rows = A.n_cols = n;
+    A.rp.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      for (int j = i - 1; j <= i + 1; ++j)
+        if (j >= 0 && j < n) {
+          A.ci.push_back(j);
+          A.v.push_back(j == i ? 4.0 : -2.0);
+        }
+      A.rp[i + 1] = static_cast<int64_t>(A.ci.size());
+    }
+    expect(std::fabs(gershgorin_scaled(A) - 2.0) < 1e-14, "scaled Gershgorin bound");
+  }
+  std::printf("%d failure(s)\n", failures);
+  return failures ? 1 : 0;
+}

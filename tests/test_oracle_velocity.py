@@ -1,0 +1,153 @@
+"""Pins of the oracle's velocity correction, loss and chained projections.
+
+* Pi_1 reproduces linear velocities exactly: coefficients are the field's
+  value at the centroid and its gradient times h_E (App. A monomials);
+* the pressure-gradient operator returns the exact gradient of a polynomial
+  pressure of the method's order (the gradient of P_k lies in the linear
+  cell field for k <= 2);
+* a gradient velocity u = grad q is removed entirely by the projection
+  (s = 0), the patch test of the whole correction;
+* the cell mass matrix integrates a linear field's square exactly (closed
+  form on the uncut cubes);
+* the vertex average of a globally linear field is that field at the vertices;
+* gradients of the loss and of the chained loss equal central finite
+  differences (the maps are linear and the losses quadratic, so the
+  difference quotient is exact up to rounding).
+"""
+import numpy as np
+import pytest
+
+from oracle import velocity as vel
+from oracle.vem import CellGeometry
+from test_oracle_global import _dof_values, _poly
+
+
+def _linear_field(pb, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(3)
+    Gm = rng.standard_normal((3, 3))
+    X = pb.vertices
+    return a, Gm, (a[None, :] + X @ Gm.T).ravel()
+
+
+@pytest.mark.parametrize("fx", ["c1_small", "c3_small", "c4_small"])
+def test_pi1_reproduces_linear_velocity(fx, request):
+    pb = request.getfixturevalue(fx)
+    o = vel.operators(pb)
+    a, Gm, u = _linear_field(pb, 3)
+    s = (o["Pi"] @ u).reshape(-1, 3, 4)
+    for E, (gd, verts, em, g) in enumerate(pb.asm.cells):
+        ref = np.concatenate([(a + Gm @ g.xc)[:, None], Gm * g.hc], axis=1)
+        assert np.abs(s[E] - ref).max() < 1e-9 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("fx", ["c1_small", "c3_small", "c4_small"])
+def test_gradient_operator_exact_on_polynomials(fx, request):
+    pb = request.getfixturevalue(fx)
+    if pb.w.dirichlet_top:
+        pytest.skip("a polynomial pressure does not vanish on the Dirichlet face")
+    o = vel.operators(pb)
+    q, grad = _poly(pb.k, 9)
+    p = _dof_values(pb, 0, q)
+    s = (o["G"] @ p).reshape(-1, 3, 4)
+    n_thin = 0
+    for E, (gd, verts, em, g) in enumerate(pb.asm.cells):
+        g0 = grad(g.xc)[0]
+        if pb.k == 1:
+            ref = np.concatenate([g0[:, None], np.zeros((3, 3))], axis=1)
+        else:
+            # the Hessian of q by central differences of the exact gradient (grad is linear)
+            H = np.stack([(grad(g.xc + e)[0] - grad(g.xc - e)[0]) / 2.0 for e in np.eye(3)], axis=1)
+            ref = np.concatenate([g0[:, None], H * g.hc], axis=1)
+        err = np.abs(s[E] - ref)
+        scale = max(1.0, np.abs(ref).max())
+        # a cell of thickness tau h_E resolves the curvature across itself from
+        # DOF differences of relative size tau^2 (rounding ~1e-16 / tau^2): on
+        # the 1e-5 sheet's slivers only the gradient at the centroid is pinned
+        tau = g.basis.s.min() / g.hc
+        if tau > 1e-3:
+            assert err.max() < 1e-8 * scale
+        else:
+            n_thin += 1
+            assert err[:, 0].max() < 1e-6 * scale
+    assert n_thin == 0 or fx == "c4_small"
+
+
+@pytest.mark.parametrize("fx", ["c3_small", "c4_small"])
+def test_gradient_velocity_is_removed(fx, request):
+    """A gradient velocity u = grad q (q quadratic, so u is linear and exact in V_1) projects to zero."""
+    pb = request.getfixturevalue(fx)
+    rng = np.random.default_rng(4)
+    # q quadratic, so grad q is linear and exactly representable in V_1
+    A = rng.standard_normal((3, 3))
+    A = A + A.T
+    c = rng.standard_normal(3)
+    X = pb.vertices
+    u = (X @ A + c[None, :]).ravel()          # grad of 0.5 x^T A x + c.x
+    s, _ = vel.project(pb, u)
+    S = np.abs(s).reshape(-1, 3, 4)
+    scale = np.abs(vel.operators(pb)["Pi"] @ u).max()
+    # sliver cells (thickness below 1e-3 h_E) only pin the centroid value,
+    # as in the gradient-operator pin above
+    thin = np.array([g.basis.s.min() / g.hc <= 1e-3 for (gd, verts, em, g) in pb.asm.cells])
+    assert S[~thin].max() < 1e-8 * scale
+    assert S[:, :, 0].max() < 1e-6 * scale
+    assert thin.sum() == 0 or fx == "c4_small"
+
+
+def test_mass_matrix_closed_form_on_cubes(c3_small):
+    pb = c3_small
+    o = vel.operators(pb)
+    M = o["M"]
+    n_checked = 0
+    for E, (gd, verts, em, g) in enumerate(pb.asm.cells):
+        if len(verts) != 8 or abs(g.volume - round(g.volume ** (1 / 3) * pb.w.N) ** 3 / pb.w.N ** 3) > 1e-12:
+            continue
+        side = g.volume ** (1.0 / 3.0)
+        ref = np.diag([side ** 3] + [side ** 5 / (12.0 * g.hc ** 2)] * 3)
+        blk = M[12 * E:12 * E + 4, 12 * E:12 * E + 4].toarray()
+        assert np.abs(blk - ref).max() < 1e-12 * side ** 3
+        n_checked += 1
+    assert n_checked > 10
+
+
+@pytest.mark.parametrize("fx", ["c1_small", "c3_small"])
+def test_average_of_global_linear_field(fx, request):
+    pb = request.getfixturevalue(fx)
+    o = vel.operators(pb)
+    a, Gm, u = _linear_field(pb, 5)
+    s = o["Pi"] @ u                             # the same linear field on every cell
+    assert np.abs(o["Av"] @ s - u).max() < 1e-9 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("fx", ["c3_small", "c4_small"])
+def test_loss_gradient_matches_finite_differences(fx, request):
+    import synth
+    pb = request.getfixturevalue(fx)
+    o = vel.operators(pb)
+    u = synth.fourier_field(pb.vertices, 0).ravel()
+    t = o["Pi"] @ synth.fourier_field(pb.vertices, 1).ravel()
+    L, g = vel.loss_and_gradient(pb, u, t)
+    for seed in (100, 101):
+        d = synth.normal_field(pb.vertices, seed).ravel()
+        eps = 1e-2 * np.linalg.norm(u) / np.linalg.norm(d)
+        Lp = vel.loss(pb, vel.project(pb, u + eps * d)[0], t)
+        Lm = vel.loss(pb, vel.project(pb, u - eps * d)[0], t)
+        fd = (Lp - Lm) / (2 * eps)
+        assert abs(fd - g @ d) <= 1e-7 * max(abs(fd), 1e-3 * L)
+
+
+def test_chain_gradient_matches_finite_differences(c3_small):
+    import synth
+    pb = c3_small
+    o = vel.operators(pb)
+    K = 3
+    u0 = synth.fourier_field(pb.vertices, 0).ravel()
+    rng = np.random.default_rng(1000)
+    eps = [0.1 * rng.standard_normal(u0.shape) for _ in range(K - 1)]
+    targets = [o["Pi"] @ synth.fourier_field(pb.vertices, 2000 + k).ravel() for k in range(K)]
+    L, g = vel.chain(pb, u0, eps, targets)
+    d = synth.normal_field(pb.vertices, 102).ravel()
+    h = 1e-2 * np.linalg.norm(u0) / np.linalg.norm(d)
+    fd = (vel.chain(pb, u0 + h * d, eps, targets)[0] - vel.chain(pb, u0 - h * d, eps, targets)[0]) / (2 * h)
+    assert abs(fd - g @ d) <= 1e-7 * max(abs(fd), 1e-3 * L)

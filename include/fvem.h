@@ -90,7 +90,21 @@ typedef struct {
  *                 right-hand side); be_len is the length of be_val.
  *  component      [n_dof of level 0]: id of the pure-Neumann component of
  *                 each free DOF (0 .. n_components-1), or -1 where the
- *                 component is anchored by Dirichlet DOFs. */
+ *                 component is anchored by Dirichlet DOFs.
+ *  vc_off/vc_val  optional velocity-correction block of each level-0 cell
+ *                 (NULL: the velocity operators below are unavailable), at
+ *                 vc_val[vc_off[c]], row-major, on the scaled linear
+ *                 monomials z = [1, (x - x_E)/h_E] of App. A:
+ *                   Pi1 (4 x n_vE): one velocity component's vertex values ->
+ *                       coefficients of its linear projection Pi_1;
+ *                   Gk (3 x 4 x n_E): pressure DOFs -> coefficients of
+ *                       d/dx_c of Pi_k p, c = 0..2 (Sec. 3.3 correction);
+ *                   M1 (4 x 4): int_E z z^T;
+ *                 cells of identical shape may share a block; vc_len is the
+ *                 length of vc_val.
+ *  cell_geom      [n_cells x 5] centroid x_E, h_E (diameter) and volume of
+ *                 each level-0 cell (with vc_off).
+ *  vert_xyz       [n_vert x 3] velocity vertex coordinates (with vc_off). */
 typedef struct {
     int32_t n_levels;
     const fvem_level_desc *levels;
@@ -105,6 +119,11 @@ typedef struct {
     int64_t be_len;
     const int32_t *component;
     int32_t n_components;
+    const int64_t *vc_off;
+    const double *vc_val;
+    int64_t vc_len;
+    const double *cell_geom;
+    const double *vert_xyz;
 } fvem_grid_desc;
 
 /* Hierarchy options.  Zero-initialised fields take the defaults in brackets. */
@@ -171,11 +190,46 @@ typedef enum {
     FVEM_OP_BT = 2,       /* y[3 n_vert] = B^T x[n_dof0] */
     FVEM_OP_VCYCLE = 3,   /* y[n_dof0] = M x: one V-cycle of the preconditioner (FP64) */
     FVEM_OP_VCYCLE32 = 4, /* the same V-cycle with FP32 smoothing and transfers */
-    FVEM_OP_PROJECT = 5   /* y = P_perp x (zero mean per pure-Neumann component) */
+    FVEM_OP_PROJECT = 5,  /* y = P_perp x (zero mean per pure-Neumann component) */
+    /* velocity operators (need vc_off at build).  A cell field holds 12
+     * values per level-0 cell, ordered (cell, component c, coefficient a) on
+     * the monomials z of vc_val. */
+    FVEM_OP_PI1 = 6,      /* y[12 n_cells] = Pi_1 x[3 n_vert] */
+    FVEM_OP_PI1T = 7,     /* y[3 n_vert] = Pi_1^T x[12 n_cells] */
+    FVEM_OP_G = 8,        /* y[12 n_cells] = grad Pi_k x[n_dof0] */
+    FVEM_OP_GT = 9,       /* y[n_dof0] = (grad Pi_k)^T x[12 n_cells] */
+    FVEM_OP_MASS = 10,    /* y[12 n_cells] = blockdiag(M1) x[12 n_cells] */
+    FVEM_OP_AV = 11,      /* y[3 n_vert] = Av x[12 n_cells]: each vertex gets the
+                             volume-weighted mean of its cells' fields at the vertex */
+    FVEM_OP_AVT = 12      /* y[12 n_cells] = Av^T x[3 n_vert] */
 } fvem_op;
+
+/* op | FVEM_APPLY_ACCUMULATE adds to y instead of overwriting it (all ops
+ * but VCYCLE, VCYCLE32 and PROJECT). */
+#define FVEM_APPLY_ACCUMULATE 0x100
 
 fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x_dev, double *y_dev,
                        void *hip_stream);
+
+/* Projected velocity (Sec. 3.3 correction after the Sec. 3.1 solve):
+ * p = fvem_solve(u), s = Pi_1 u - grad Pi_k p.  u_dev [3 n_vert], s_dev
+ * [12 n_cells]; p_dev [n_dof0] receives the pressure unless NULL.  Same
+ * options, stats, errors and stream rules as fvem_solve; needs vc_off. */
+fvem_status fvem_project_velocity(fvem_hierarchy *h, const double *u_dev, double *s_dev, double *p_dev,
+                                  const fvem_solve_opts *so, fvem_solve_stats *st, void *hip_stream);
+
+/* Transpose of u -> s: g_u = Pi_1^T g_s + B^T P_perp K^+ P_perp (-(grad Pi_k)^T g_s).
+ * gs_dev [12 n_cells], gu_dev [3 n_vert]. */
+fvem_status fvem_project_velocity_adjoint(fvem_hierarchy *h, const double *gs_dev, double *gu_dev,
+                                          const fvem_solve_opts *so, fvem_solve_stats *st,
+                                          void *hip_stream);
+
+/* Loss of a cell field against a target: L = sum_E int_E |s_E - t_E|^2
+ * = (s - t)^T blockdiag(M1) (s - t), written to *loss_host (host memory);
+ * when gs_dev is not NULL it receives scale * dL/ds = 2 scale M1 (s - t).
+ * Deterministic (fixed-order reduction); synchronises the stream. */
+fvem_status fvem_velocity_loss(fvem_hierarchy *h, const double *s_dev, const double *t_dev, double scale,
+                               double *loss_host, double *gs_dev, void *hip_stream);
 
 /* Level data for inspection: copies level l's operator A_l (FP64 CSR as
  * built on the device) to caller-owned host arrays.  Call first with NULL
@@ -186,6 +240,9 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
 /* Sizes: number of levels, and n_dof / nnz of level l. */
 fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n_dof0,
                                 int64_t *n_vert, int64_t *device_bytes);
+
+/* Number of level-0 cells carrying velocity fields (0 without vc_off). */
+fvem_status fvem_hierarchy_cells(fvem_hierarchy *h, int64_t *n_cells);
 
 void fvem_hierarchy_destroy(fvem_hierarchy *h);
 

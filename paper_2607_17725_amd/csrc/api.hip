@@ -11,6 +11,7 @@
 //   V-cycle's operators and vectors are FP32 and the coarsest solve FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <memory>
 #include <cmath>
@@ -110,6 +111,10 @@ struct fvem_hierarchy {
   fvem::DevCSR B, BT;
   int64_t nvert = 0, n0 = 0;
   int32_t *perm0 = nullptr, *iperm0 = nullptr;   // level-0 order and its inverse (device)
+  // velocity operators on cell fields (12 values per level-0 cell)
+  int64_t ncell_v = 0;
+  fvem::DevCSR Pi, PiT, Gr, GrT, Ms, Av, AvT;
+  double *vs1 = nullptr, *vs2 = nullptr;
   int32_t *comp0 = nullptr;
   int ncomp0 = 0;
   // coarsest level
@@ -207,6 +212,85 @@ static std::vector<int32_t> inverse(const std::vector<int32_t> &order) {
   std::vector<int32_t> inv(order.size());
   for (size_t i = 0; i < order.size(); ++i) inv[order[i]] = static_cast<int32_t>(i);
   return inv;
+}
+
+// Velocity operators on cell fields (row 12 E + 4 c + a: component c,
+// coefficient a of cell E on the monomials [1, (x - x_E)/h_E]), assembled
+// as CSR from the per-cell blocks: Pi_1, grad Pi_k (columns in the level
+// order), the block-diagonal mass and the volume-weighted vertex average.
+static void build_velocity(fvem_hierarchy *h, const fvem_grid_desc *g, const HostCells &c0,
+                           const std::vector<int32_t> &inv0, hipStream_t s) {
+  const int64_t nc = c0.n_cells, nv = g->n_vert;
+  check(nv > 0 && g->vc_val && g->vc_len >= 0 && g->cell_geom && g->vert_xyz, "velocity data incomplete");
+  check(finite_all(g->vc_val, g->vc_len), "velocity blocks: non-finite value");
+  check(finite_all(g->cell_geom, 5 * nc), "cell geometry: non-finite value");
+  check(finite_all(g->vert_xyz, 3 * nv), "vertex coordinates: non-finite value");
+  std::vector<double> W(nv, 0.0);   // volume around each vertex
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t nvE = g->cell_vptr[c + 1] - g->cell_vptr[c], nE = c0.ptr[c + 1] - c0.ptr[c];
+    check(g->vc_off[c] >= 0 && g->vc_off[c] + 4 * nvE + 12 * nE + 16 <= g->vc_len, "velocity block out of range");
+    check(g->cell_geom[5 * c + 3] > 0 && g->cell_geom[5 * c + 4] > 0, "cell diameter or volume not positive");
+    for (int64_t q = g->cell_vptr[c]; q < g->cell_vptr[c + 1]; ++q) W[g->cell_vert[q]] += g->cell_geom[5 * c + 4];
+  }
+  HostCSR Pi, Gr, Ms, AvT;
+  for (HostCSR *A : {&Pi, &Gr, &Ms, &AvT}) {
+    A->n_rows = 12 * nc;
+    A->rp.assign(12 * nc + 1, 0);
+  }
+  Pi.n_cols = 3 * nv;
+  Gr.n_cols = h->n0;
+  Ms.n_cols = 12 * nc;
+  AvT.n_cols = 3 * nv;
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t v0 = g->cell_vptr[c], nvE = g->cell_vptr[c + 1] - v0, nE = c0.ptr[c + 1] - c0.ptr[c];
+    const double *blk = g->vc_val + g->vc_off[c];
+    const double *pi1 = blk, *gk = blk + 4 * nvE, *m1 = blk + 4 * nvE + 12 * nE;
+    const double *geo = g->cell_geom + 5 * c;
+    for (int comp = 0; comp < 3; ++comp)
+      for (int a = 0; a < 4; ++a) {
+        const int64_t r = 12 * c + 4 * comp + a;
+        for (int64_t v = 0; v < nvE; ++v) {
+          Pi.ci.push_back(3 * g->cell_vert[v0 + v] + comp);
+          Pi.v.push_back(pi1[a * nvE + v]);
+        }
+        Pi.rp[r + 1] = static_cast<int64_t>(Pi.ci.size());
+        row.clear();
+        for (int64_t q = 0; q < nE; ++q) {
+          const int32_t d = c0.dof[c0.ptr[c] + q];
+          if (d >= 0) row.emplace_back(inv0[d], gk[(comp * 4 + a) * nE + q]);
+        }
+        std::sort(row.begin(), row.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (const auto &e : row) {
+          Gr.ci.push_back(e.first);
+          Gr.v.push_back(e.second);
+        }
+        Gr.rp[r + 1] = static_cast<int64_t>(Gr.ci.size());
+        for (int b = 0; b < 4; ++b) {
+          Ms.ci.push_back(static_cast<int32_t>(12 * c + 4 * comp + b));
+          Ms.v.push_back(m1[a * 4 + b]);
+        }
+        Ms.rp[r + 1] = static_cast<int64_t>(Ms.ci.size());
+        for (int64_t v = 0; v < nvE; ++v) {
+          const int32_t gv = g->cell_vert[v0 + v];
+          const double za = a == 0 ? 1.0 : (g->vert_xyz[3 * gv + a - 1] - geo[a - 1]) / geo[3];
+          AvT.ci.push_back(3 * gv + comp);
+          AvT.v.push_back(geo[4] / W[gv] * za);
+        }
+        AvT.rp[r + 1] = static_cast<int64_t>(AvT.ci.size());
+      }
+  }
+  check(12 * nc < (int64_t(1) << 31) && 3 * nv < (int64_t(1) << 31), "cell field too large for int32 columns");
+  h->ncell_v = nc;
+  h->Pi = upload_csr(h, Pi, false, s);
+  h->PiT = upload_csr(h, transpose(Pi), false, s);
+  h->Gr = upload_csr(h, Gr, false, s);
+  h->GrT = upload_csr(h, transpose(Gr), false, s);
+  h->Ms = upload_csr(h, Ms, false, s);
+  h->AvT = upload_csr(h, AvT, false, s);
+  h->Av = upload_csr(h, transpose(AvT), false, s);
+  h->vs1 = h->mem.alloc<double>(12 * nc);
+  h->vs2 = h->mem.alloc<double>(12 * nc);
 }
 
 static void cheb_coefficients(Level &L, int deg, double lower) {
@@ -368,6 +452,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     h->BT = upload_csr(h, transpose(Bh), false, s);
   }
   h->comp0 = h->mem.upload(comp0, s);
+  if (g->vc_off) build_velocity(h, g, c0, inv[0], s);
   progress("hierarchy: operators uploaded");
 
   // coarsest level: dense semi-definite factorisation and generalised inverse
@@ -539,6 +624,14 @@ static void precondition(fvem_hierarchy *h, const double *r, double *z, bool mix
   if (h->ncomp0) project_components(n, z, h->comp0, h->ncomp0, h->partial, h->mean, s);
 }
 
+static void dots_host_n(fvem_hierarchy *h, int64_t n, int nd, const double *a0, const double *b0, const double *a1,
+                        const double *b1, const double *a2, const double *b2, double *out, hipStream_t s) {
+  dots(n, nd, a0, b0, a1, b1, a2, b2, h->partial, h->dotout, s);
+  HIPCHECK(hipMemcpyAsync(h->host, h->dotout, sizeof(double) * nd, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (int j = 0; j < nd; ++j) out[j] = h->host[j];
+}
+
 static void dots_host(fvem_hierarchy *h, int nd, const double *a0, const double *b0, const double *a1,
                       const double *b1, const double *a2, const double *b2, double *out, hipStream_t s) {
   dots(h->n0, nd, a0, b0, a1, b1, a2, b2, h->partial, h->dotout, s);
@@ -618,10 +711,18 @@ static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const
   return status;
 }
 
+enum SolveKind { SOLVE_FORWARD, SOLVE_ADJOINT, SOLVE_VELOCITY, SOLVE_VELOCITY_ADJOINT };
+
+// One solve with timing and stats.  SOLVE_VELOCITY: out = s = Pi_1 u -
+// grad Pi_k p (p also to p_out unless null); SOLVE_VELOCITY_ADJOINT:
+// out = g_u = Pi_1^T g_s + B^T K^+ (-(grad Pi_k)^T g_s).
 static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out, const fvem_solve_opts *so,
-                                fvem_solve_stats *st, hipStream_t s, bool adjoint) {
-  const bool velocity = !so || so->input == FVEM_INPUT_VELOCITY;
+                                fvem_solve_stats *st, hipStream_t s, SolveKind kind, double *p_out = nullptr) {
+  const bool adjoint = kind == SOLVE_ADJOINT;
+  const bool vel_op = kind == SOLVE_VELOCITY || kind == SOLVE_VELOCITY_ADJOINT;
+  const bool velocity = vel_op || !so || so->input == FVEM_INPUT_VELOCITY;
   if (velocity && h->nvert == 0) throw SetupError{FVEM_ERR_INVALID, "no divergence operator in this hierarchy"};
+  if (vel_op && h->ncell_v == 0) throw SetupError{FVEM_ERR_INVALID, "no velocity operators in this hierarchy"};
   h->profiling = so && so->profile;
   h->ev_used = 0;
   hipEvent_t e0, e1;
@@ -631,7 +732,18 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
   // caller's DOF order <-> level order at the boundary of the solve
   const int64_t n = h->n0;
   fvem_status stt;
-  if (!adjoint) {
+  if (kind == SOLVE_VELOCITY) {
+    spmv<double>(h->B.d(), in, h->q, s);
+    stt = pcg(h, h->q, h->lam, so, st, s);
+    if (p_out) gather(n, h->iperm0, h->lam, p_out, s);
+    spmv<double>(h->Pi.d(), in, out, s);
+    residual<double>(h->Gr.d(), h->lam, out, out, s);   // s = Pi_1 u - G p
+  } else if (kind == SOLVE_VELOCITY_ADJOINT) {
+    spmv_scaled(h->GrT.d(), in, h->q, -1.0, s);         // g_p = -G^T g_s (level order)
+    stt = pcg(h, h->q, h->lam, so, st, s);
+    spmv<double>(h->BT.d(), h->lam, out, s);
+    spmv_add<double>(h->PiT.d(), in, out, s);
+  } else if (!adjoint) {
     const double *rhs = h->q;
     if (velocity) spmv<double>(h->B.d(), in, h->q, s);
     else gather(n, h->perm0, in, h->q, s);
@@ -730,7 +842,7 @@ fvem_status fvem_solve(fvem_hierarchy *h, const double *in_dev, double *p_dev, c
     g_last_error = "another solve is running on this handle";
     return FVEM_ERR_BUSY;
   }
-  return guard([&] { return solve_common(h, in_dev, p_dev, so, st, static_cast<hipStream_t>(hip_stream), false); });
+  return guard([&] { return solve_common(h, in_dev, p_dev, so, st, static_cast<hipStream_t>(hip_stream), SOLVE_FORWARD); });
 }
 
 fvem_status fvem_solve_adjoint(fvem_hierarchy *h, const double *gp_dev, double *gu_dev, const fvem_solve_opts *so,
@@ -744,7 +856,77 @@ fvem_status fvem_solve_adjoint(fvem_hierarchy *h, const double *gp_dev, double *
     g_last_error = "another solve is running on this handle";
     return FVEM_ERR_BUSY;
   }
-  return guard([&] { return solve_common(h, gp_dev, gu_dev, so, st, static_cast<hipStream_t>(hip_stream), true); });
+  return guard([&] { return solve_common(h, gp_dev, gu_dev, so, st, static_cast<hipStream_t>(hip_stream), SOLVE_ADJOINT); });
+}
+
+fvem_status fvem_project_velocity(fvem_hierarchy *h, const double *u_dev, double *s_dev, double *p_dev,
+                                  const fvem_solve_opts *so, fvem_solve_stats *st, void *hip_stream) {
+  if (!h || !u_dev || !s_dev) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  BusyGuard bg(h);
+  if (!bg.ok) {
+    g_last_error = "another solve is running on this handle";
+    return FVEM_ERR_BUSY;
+  }
+  return guard([&] {
+    return solve_common(h, u_dev, s_dev, so, st, static_cast<hipStream_t>(hip_stream), SOLVE_VELOCITY, p_dev);
+  });
+}
+
+fvem_status fvem_project_velocity_adjoint(fvem_hierarchy *h, const double *gs_dev, double *gu_dev,
+                                          const fvem_solve_opts *so, fvem_solve_stats *st, void *hip_stream) {
+  if (!h || !gs_dev || !gu_dev) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  BusyGuard bg(h);
+  if (!bg.ok) {
+    g_last_error = "another solve is running on this handle";
+    return FVEM_ERR_BUSY;
+  }
+  return guard([&] {
+    return solve_common(h, gs_dev, gu_dev, so, st, static_cast<hipStream_t>(hip_stream), SOLVE_VELOCITY_ADJOINT);
+  });
+}
+
+fvem_status fvem_velocity_loss(fvem_hierarchy *h, const double *s_dev, const double *t_dev, double scale,
+                               double *loss_host, double *gs_dev, void *hip_stream) {
+  if (!h || !s_dev || !t_dev || !loss_host) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  BusyGuard bg(h);
+  if (!bg.ok) {
+    g_last_error = "another call is running on this handle";
+    return FVEM_ERR_BUSY;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  return guard([&] {
+    check(h->ncell_v > 0, "no velocity operators in this hierarchy");
+    const int64_t m = 12 * h->ncell_v;
+    lincomb(m, 1.0, s_dev, -1.0, t_dev, h->vs1, s);     // d = s - t
+    spmv<double>(h->Ms.d(), h->vs1, h->vs2, s);          // w = M d
+    double d[1];
+    dots_host_n(h, m, 1, h->vs1, h->vs2, nullptr, nullptr, nullptr, nullptr, d, s);
+    if (!std::isfinite(d[0])) throw SetupError{FVEM_ERR_NONFINITE, "non-finite loss"};
+    *loss_host = d[0];
+    if (gs_dev) {
+      lincomb(m, 2.0 * scale, h->vs2, 0.0, nullptr, gs_dev, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_hierarchy_cells(fvem_hierarchy *h, int64_t *n_cells) {
+  if (!h || !n_cells) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  *n_cells = h->ncell_v;
+  return FVEM_OK;
 }
 
 fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y, void *hip_stream) {
@@ -758,9 +940,33 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
     return FVEM_ERR_BUSY;
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const bool acc = (op & FVEM_APPLY_ACCUMULATE) != 0;
+  op &= ~FVEM_APPLY_ACCUMULATE;
   return guard([&] {
     const int64_t n = h->n0;
+    if (op >= FVEM_OP_PI1 && op <= FVEM_OP_AVT) check(h->ncell_v > 0, "no velocity operators in this hierarchy");
+    if (acc)
+      check(op == FVEM_OP_BT || op == FVEM_OP_PI1 || op == FVEM_OP_PI1T || op == FVEM_OP_G || op == FVEM_OP_MASS ||
+                op == FVEM_OP_AV || op == FVEM_OP_AVT,
+            "accumulation is not available for this operator");
+    auto csr = [&](const DevCSR &A, const double *xx) {
+      if (acc) spmv_add<double>(A.d(), xx, y, s);
+      else spmv<double>(A.d(), xx, y, s);
+    };
     switch (op) {
+      case FVEM_OP_PI1: csr(h->Pi, x); break;
+      case FVEM_OP_PI1T: csr(h->PiT, x); break;
+      case FVEM_OP_G:
+        gather(n, h->perm0, x, h->p, s);
+        csr(h->Gr, h->p);
+        break;
+      case FVEM_OP_GT:
+        spmv<double>(h->GrT.d(), x, h->q, s);
+        gather(n, h->iperm0, h->q, y, s);
+        break;
+      case FVEM_OP_MASS: csr(h->Ms, x); break;
+      case FVEM_OP_AV: csr(h->Av, x); break;
+      case FVEM_OP_AVT: csr(h->AvT, x); break;
       case FVEM_OP_K:
         gather(n, h->perm0, x, h->p, s);
         spmv<double>(h->lv[0].A.d(), h->p, h->q, s);
@@ -774,7 +980,7 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
       case FVEM_OP_BT:
         check(h->nvert > 0, "no divergence operator");
         gather(n, h->perm0, x, h->p, s);
-        spmv<double>(h->BT.d(), h->p, y, s);
+        csr(h->BT, h->p);
         break;
       case FVEM_OP_VCYCLE:
       case FVEM_OP_VCYCLE32: {
@@ -948,6 +1154,11 @@ fvem_status fvem_grid_describe(fvem_grid *g, fvem_grid_desc *d) {
   d->be_len = static_cast<int64_t>(o.be_val.size());
   d->component = o.component.data();
   d->n_components = o.n_components;
+  d->vc_off = o.vc_off.data();
+  d->vc_val = o.vc_val.data();
+  d->vc_len = static_cast<int64_t>(o.vc_val.size());
+  d->cell_geom = o.cell_geom.data();
+  d->vert_xyz = g->xflat.data();
   return FVEM_OK;
 }
 

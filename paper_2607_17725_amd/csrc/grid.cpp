@@ -1214,6 +1214,7 @@ struct BuilderImpl {
     o.cell_vert.assign(M.cvert.begin(), M.cvert.end());
     o.ke_off.assign(nc, 0);
     o.be_off.assign(nc, 0);
+    o.vc_off.assign(nc, 0);
     std::vector<vem::CellData> data(nc);
     std::vector<int64_t> tmpl(nc, -1);
     std::unordered_map<int, int64_t> shape;   // plain cube side -> first cell
@@ -1233,10 +1234,27 @@ struct BuilderImpl {
         o.ke_val.insert(o.ke_val.end(), data[c].K.begin(), data[c].K.end());
         o.be_off[c] = static_cast<int64_t>(o.be_val.size());
         o.be_val.insert(o.be_val.end(), data[c].B.begin(), data[c].B.end());
+        o.vc_off[c] = static_cast<int64_t>(o.vc_val.size());
+        o.vc_val.insert(o.vc_val.end(), data[c].V.begin(), data[c].V.end());
       } else {
         o.ke_off[c] = o.ke_off[src];
         o.be_off[c] = o.be_off[src];
+        o.vc_off[c] = o.vc_off[src];
       }
+    }
+    // cell geometry for the velocity operators: centroid, diameter, volume
+    o.cell_geom.assign(5 * nc, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+      double hE = 0;
+      for (int64_t a = M.cvptr[c]; a < M.cvptr[c + 1]; ++a)
+        for (int64_t b = a + 1; b < M.cvptr[c + 1]; ++b) hE = std::max(hE, norm(M.X[M.cvert[a]] - M.X[M.cvert[b]]));
+      const V3 xc = tmpl[c] < 0 ? data[c].basis.xc : M.ccen[c];
+      o.cell_geom[5 * c] = xc.x;
+      o.cell_geom[5 * c + 1] = xc.y;
+      o.cell_geom[5 * c + 2] = xc.z;
+      o.cell_geom[5 * c + 3] = hE;
+      o.cell_geom[5 * c + 4] = M.cvol[c];
     }
     o.n_shared_blocks = static_cast<int64_t>(shape.size());
     // pure-Neumann components: connected cells (sharing DOFs) without an eliminated DOF

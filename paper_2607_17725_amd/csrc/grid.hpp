@@ -40,8 +40,9 @@ struct CSROut {
 struct Output {
   std::vector<LevelOut> levels;
   std::vector<CSROut> P;        // P[l]: level l+1 -> level l
-  std::vector<int64_t> ke_off, be_off;
-  std::vector<double> ke_val, be_val;
+  std::vector<int64_t> ke_off, be_off, vc_off;
+  std::vector<double> ke_val, be_val, vc_val;
+  std::vector<double> cell_geom;  // [n_cells x 5] centroid, h_E, volume
   int64_t n_vert = 0;
   std::vector<geo::V3> X;       // velocity vertices
   std::vector<int64_t> cell_vptr;

@@ -61,6 +61,13 @@ struct EpiAdd {  // y += A x  (prolong-and-correct)
   __device__ void operator()(int64_t i, T a) const { y[i] += a; }
 };
 
+struct EpiScaled {  // y = alpha A x
+  using acc_t = double;
+  double *y;
+  double alpha;
+  __device__ void operator()(int64_t i, double a) const { y[i] = alpha * a; }
+};
+
 template <typename T>
 struct EpiCheb {  // d = ca d + cb dinv (b - A xin);  xout = xin + d
   using acc_t = T;
@@ -197,6 +204,10 @@ void cheb_step(const DevCSRView<T> &A, const T *b, const T *dinv, const T *xin, 
   launch_spmv(A, xin, EpiCheb<T>{b, dinv, xin, d, xout, ca, cb}, s);
 }
 
+void spmv_scaled(const DevCSRView<double> &A, const double *x, double *y, double alpha, hipStream_t s) {
+  launch_spmv(A, x, EpiScaled{y, alpha}, s);
+}
+
 template void spmv<double>(const DevCSRView<double> &, const double *, double *, hipStream_t);
 template void spmv<float>(const DevCSRView<float> &, const float *, float *, hipStream_t);
 template void residual<double>(const DevCSRView<double> &, const double *, const double *, double *,
@@ -244,6 +255,16 @@ __global__ void gather_kernel(int64_t n, const int32_t *idx, const double *x, do
 
 void gather(int64_t n, const int32_t *idx, const double *x, double *y, hipStream_t s) {
   if (n) gather_kernel<<<vgrid(n), 256, 0, s>>>(n, idx, x, y);
+}
+
+__global__ void lincomb_kernel(int64_t n, double alpha, const double *a, double beta, const double *b, double *y) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = b ? alpha * a[i] + beta * b[i] : alpha * a[i];
+}
+
+void lincomb(int64_t n, double alpha, const double *a, double beta, const double *b, double *y, hipStream_t s) {
+  if (n) lincomb_kernel<<<vgrid(n), 256, 0, s>>>(n, alpha, a, beta, b, y);
 }
 
 __global__ void cast_scale_kernel_df(int64_t n, const double *a, float *b, double s) {

@@ -41,6 +41,7 @@ void cheb_step(const DevSELLView<T> &A, const T *b, const T *dinv, const T *xin,
 template <typename T> void spmv(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s);
 template <typename T> void residual(const DevCSRView<T> &A, const T *x, const T *b, T *r, hipStream_t s);
 template <typename T> void spmv_add(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s);
+void spmv_scaled(const DevCSRView<double> &A, const double *x, double *y, double alpha, hipStream_t s);  // y = alpha A x
 template <typename T>
 void cheb_step(const DevCSRView<T> &A, const T *b, const T *dinv, const T *xin, T *d, T *xout, T ca, T cb,
                hipStream_t s);
@@ -48,6 +49,8 @@ template <typename T> void cheb_first(int64_t n, const T *b, const T *dinv, T *d
 
 // vectors
 void gather(int64_t n, const int32_t *idx, const double *x, double *y, hipStream_t s);   // y[i] = x[idx[i]]
+// y = alpha a + beta b (b may be null: y = alpha a); y may alias a or b
+void lincomb(int64_t n, double alpha, const double *a, double beta, const double *b, double *y, hipStream_t s);
 void cast_scale(int64_t n, const double *a, float *b, double s, hipStream_t st);
 void cast_scale(int64_t n, const float *a, double *b, double s, hipStream_t st);
 void cast_f64_f32(int64_t n, const double *a, float *b, hipStream_t s);

@@ -527,6 +527,64 @@ static CellData build(const Cell &c, int k, bool stiffness, bool with_div) {
         out.B[r * (3 * nv) + 3 * v + comp] = s;
       }
   }
+  // Velocity correction (Sec. 3.3: Pi_1 u - grad Pi_k p per cell) on the
+  // paper's scaled linear monomials z = (x - x_E)/h_E.  Tz maps coefficients
+  // on this basis's linear part [1, y] to [1, z]: y_d = sum_i R_id h_E z_i / s_d.
+  double Tz[4][4] = {{1, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) Tz[1 + i][1 + d] = bs.R[i][d] * bs.hE / bs.s[d];
+  out.V.assign(4 * nv + 12 * nE + 16, 0.0);
+  for (int a = 0; a < 4; ++a)
+    for (int v = 0; v < nv; ++v) {
+      double s = 0;
+      for (int b = 0; b < 4; ++b) s += Tz[a][b] * P1[b * nv + v];
+      out.V[a * nv + v] = s;
+    }
+  auto lin_index = [](const int e[3]) {
+    for (int a = 0; a < 4; ++a)
+      if (EXP3[a][0] == e[0] && EXP3[a][1] == e[1] && EXP3[a][2] == e[2]) return a;
+    return -1;
+  };
+  for (int comp = 0; comp < 3; ++comp) {
+    // C[a][b]: d/dx_comp of basis monomial b on the linear monomials [1, y]
+    double C[4][10] = {};
+    for (int b = 1; b < Nk; ++b)
+      for (int d = 0; d < 3; ++d) {
+        const int eb = EXP3[b][d];
+        if (!eb) continue;
+        int ex[3] = {EXP3[b][0], EXP3[b][1], EXP3[b][2]};
+        ex[d] -= 1;
+        C[lin_index(ex)][b] += bs.R[comp][d] / bs.s[d] * eb;
+      }
+    // grad_comp Pi_k = T C Pi*
+    double TC[4][10] = {};
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < Nk; ++b)
+        for (int t = 0; t < 4; ++t) TC[a][b] += Tz[a][t] * C[t][b];
+    for (int a = 0; a < 4; ++a)
+      for (int r = 0; r < nE; ++r) {
+        double s = 0;
+        for (int b = 0; b < Nk; ++b) s += TC[a][b] * out.Pis[b * nE + r];
+        out.V[4 * nv + (comp * 4 + a) * nE + r] = s;
+      }
+  }
+  // mass of [1, z]: z_i = sum_d R_id s_d y_d / h_E
+  double A[4][4] = {};   // A[i][d]: z_i on [1, y]
+  A[0][0] = 1.0;
+  for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) A[1 + i][1 + d] = bs.R[i][d] * bs.s[d] / bs.hE;
+  double My[4][4];       // int_E of products of [1, y]
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      My[a][b] = M.at(EXP3[a][0] + EXP3[b][0], EXP3[a][1] + EXP3[b][1], EXP3[a][2] + EXP3[b][2]);
+  double *Mz = out.V.data() + 4 * nv + 12 * nE;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      double s = 0;
+      for (int c2 = 0; c2 < 4; ++c2)
+        for (int d = 0; d < 4; ++d) s += A[a][c2] * My[c2][d] * A[b][d];
+      Mz[a * 4 + b] = s;
+    }
   return out;
 }
 

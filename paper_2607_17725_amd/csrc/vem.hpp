@@ -56,6 +56,9 @@ struct CellData {
   std::vector<double> Pis;   // N_k x n_E
   std::vector<double> K;     // n_E x n_E
   std::vector<double> B;     // n_E x (3 n_v)  (only when requested)
+  // velocity-correction block (with B), on the paper's linear monomials
+  // z = [1, (x - x_E)/h_E]: Pi_1 (4 x n_v) | grad Pi_k (3 x 4 x n_E) | mass (4 x 4)
+  std::vector<double> V;
 };
 
 int npoly3(int k);

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libfvem.so")
 STATUS = {0: "OK", 1: "INVALID", 2: "HIP", 3: "OOM", 4: "NOT_SPD", 5: "NOT_CONVERGED", 6: "NONFINITE",
           7: "BUSY"}
 OP_K, OP_B, OP_BT, OP_VCYCLE, OP_VCYCLE32, OP_PROJECT = range(6)
+OP_PI1, OP_PI1T, OP_G, OP_GT, OP_MASS, OP_AV, OP_AVT = range(6, 13)
+APPLY_ACCUMULATE = 0x100
 PREC_FP64, PREC_MIXED = 0, 1
 INPUT_VELOCITY, INPUT_RHS = 0, 1
 
@@ -44,7 +46,9 @@ class _Grid(ctypes.Structure):
                 ("ke_off", ctypes.c_void_p), ("ke_val", ctypes.c_void_p), ("ke_len", ctypes.c_int64),
                 ("n_vert", ctypes.c_int64), ("cell_vptr", ctypes.c_void_p), ("cell_vert", ctypes.c_void_p),
                 ("be_off", ctypes.c_void_p), ("be_val", ctypes.c_void_p), ("be_len", ctypes.c_int64),
-                ("component", ctypes.c_void_p), ("n_components", ctypes.c_int32)]
+                ("component", ctypes.c_void_p), ("n_components", ctypes.c_int32),
+                ("vc_off", ctypes.c_void_p), ("vc_val", ctypes.c_void_p), ("vc_len", ctypes.c_int64),
+                ("cell_geom", ctypes.c_void_p), ("vert_xyz", ctypes.c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -69,7 +73,8 @@ class SolveStats(ctypes.Structure):
 
 EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_apply", "fvem_level_matrix",
            "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error", "fvem_grid_build",
-           "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy"]
+           "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy",
+           "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells"]
 
 _lib = None
 
@@ -90,6 +95,15 @@ def load(path=LIB_PATH):
         fn.restype = ctypes.c_int
     lib.fvem_apply.argtypes = [vp, i32, vp, vp, vp]
     lib.fvem_apply.restype = ctypes.c_int
+    lib.fvem_project_velocity.argtypes = [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
+    lib.fvem_project_velocity.restype = ctypes.c_int
+    lib.fvem_project_velocity_adjoint.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats),
+                                                  vp]
+    lib.fvem_project_velocity_adjoint.restype = ctypes.c_int
+    lib.fvem_velocity_loss.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
+    lib.fvem_velocity_loss.restype = ctypes.c_int
+    lib.fvem_hierarchy_cells.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.fvem_hierarchy_cells.restype = ctypes.c_int
     lib.fvem_level_matrix.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
     lib.fvem_level_matrix.restype = ctypes.c_int
     lib.fvem_hierarchy_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -177,13 +191,15 @@ class Hierarchy:
         g.levels = levels
         for name, dt in (("ke_off", np.int64), ("ke_val", np.float64), ("cell_vptr", np.int64),
                          ("cell_vert", np.int32), ("be_off", np.int64), ("be_val", np.float64),
-                         ("component", np.int32)):
+                         ("component", np.int32), ("vc_off", np.int64), ("vc_val", np.float64),
+                         ("cell_geom", np.float64), ("vert_xyz", np.float64)):
             if desc.get(name) is not None:
                 a, p = _arr(desc[name], dt)
                 keep.append(a)
                 setattr(g, name, p)
         g.ke_len = len(desc["ke_val"])
         g.be_len = len(desc["be_val"]) if desc.get("be_val") is not None else 0
+        g.vc_len = len(desc["vc_val"]) if desc.get("vc_val") is not None else 0
         g.n_vert = int(desc.get("n_vert", 0))
         g.n_components = int(desc.get("n_components", 0))
         self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift)
@@ -199,6 +215,9 @@ class Hierarchy:
         nl, n0, nv, nb = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.fvem_hierarchy_info(h, ctypes.byref(nl), ctypes.byref(n0), ctypes.byref(nv), ctypes.byref(nb)))
         self.n_levels, self.n_dof, self.n_vert, self.device_bytes = nl.value, n0.value, nv.value, nb.value
+        ncv = ctypes.c_int64()
+        _check(lib.fvem_hierarchy_cells(h, ctypes.byref(ncv)))
+        self.n_cells = ncv.value
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     def __del__(self):
@@ -247,14 +266,61 @@ class Hierarchy:
                                          ctypes.c_void_p(self.stream.cuda_stream)))
         return out, st.as_dict()
 
-    def apply(self, op, x):
+    def _op_sizes(self, op):
+        nv3, n, nc = 3 * self.n_vert, self.n_dof, 12 * self.n_cells
+        return {OP_K: (n, n), OP_B: (nv3, n), OP_BT: (n, nv3), OP_VCYCLE: (n, n), OP_VCYCLE32: (n, n),
+                OP_PROJECT: (n, n), OP_PI1: (nv3, nc), OP_PI1T: (nc, nv3), OP_G: (n, nc), OP_GT: (nc, n),
+                OP_MASS: (nc, nc), OP_AV: (nc, nv3), OP_AVT: (nv3, nc)}[op]
+
+    def apply(self, op, x, out=None, accumulate=False):
+        """y = op(x), or out += op(x) with accumulate (velocity operators and B^T)."""
         import torch
-        n_in = 3 * self.n_vert if op == OP_B else self.n_dof
-        n_out = 3 * self.n_vert if op == OP_BT else self.n_dof
-        y = torch.empty(n_out, dtype=torch.float64, device=self.device)
-        _check(load().fvem_apply(self._h, op, self._vec(x, n_in, "x"), self._vec(y, n_out, "y"),
+        n_in, n_out = self._op_sizes(op)
+        y = out if out is not None else torch.empty(n_out, dtype=torch.float64, device=self.device)
+        code = op | (APPLY_ACCUMULATE if accumulate else 0)
+        _check(load().fvem_apply(self._h, code, self._vec(x, n_in, "x"), self._vec(y, n_out, "y"),
                                  ctypes.c_void_p(self.stream.cuda_stream)))
         return y
+
+    def project_velocity(self, u, s=None, p=None, tol=1e-8, maxit=500, precision=PREC_MIXED,
+                         raise_not_converged=True):
+        """Projected velocity s = Pi_1 u - grad Pi_k p (12 values per cell), with p = K^+ P B u."""
+        import torch
+        nc = 12 * self.n_cells
+        if s is None:
+            s = torch.empty(nc, dtype=torch.float64, device=self.device)
+        pp = self._vec(p, self.n_dof, "p") if p is not None else None
+        st = SolveStats()
+        so = self._opts(tol, maxit, precision, INPUT_VELOCITY, 10, False)
+        code = load().fvem_project_velocity(self._h, self._vec(u, 3 * self.n_vert, "u"), self._vec(s, nc, "s"), pp,
+                                            ctypes.byref(so), ctypes.byref(st),
+                                            ctypes.c_void_p(self.stream.cuda_stream))
+        if code != 5 or raise_not_converged:
+            _check(code)
+        return s, st.as_dict()
+
+    def project_velocity_adjoint(self, gs, gu=None, tol=1e-8, maxit=500, precision=PREC_MIXED):
+        """g_u = Pi_1^T g_s + B^T P K^+ P (-(grad Pi_k)^T g_s), the transpose of u -> s."""
+        import torch
+        if gu is None:
+            gu = torch.empty(3 * self.n_vert, dtype=torch.float64, device=self.device)
+        st = SolveStats()
+        so = self._opts(tol, maxit, precision, INPUT_VELOCITY, 10, False)
+        _check(load().fvem_project_velocity_adjoint(self._h, self._vec(gs, 12 * self.n_cells, "g_s"),
+                                                    self._vec(gu, 3 * self.n_vert, "g_u"), ctypes.byref(so),
+                                                    ctypes.byref(st), ctypes.c_void_p(self.stream.cuda_stream)))
+        return gu, st.as_dict()
+
+    def velocity_loss(self, s, t, scale=1.0, grad=True):
+        """(L, g_s): L = sum_E int_E |s - t|^2, g_s = scale * dL/ds (None without grad)."""
+        import torch
+        nc = 12 * self.n_cells
+        gs = torch.empty(nc, dtype=torch.float64, device=self.device) if grad else None
+        L = ctypes.c_double()
+        _check(load().fvem_velocity_loss(self._h, self._vec(s, nc, "s"), self._vec(t, nc, "t"), float(scale),
+                                         ctypes.byref(L), self._vec(gs, nc, "g_s") if grad else None,
+                                         ctypes.c_void_p(self.stream.cuda_stream)))
+        return L.value, gs
 
     def level_matrix(self, level):
         """Level operator as (row_ptr, col, val) host arrays."""
@@ -335,7 +401,10 @@ class Grid:
                 "cell_vert": arr(g.cell_vert, int(vptr[-1]), ctypes.c_int32),
                 "be_off": arr(g.be_off, nc0, ctypes.c_int64), "be_val": arr(g.be_val, g.be_len, ctypes.c_double),
                 "component": arr(g.component, g.levels[0].n_dof, ctypes.c_int32),
-                "n_components": g.n_components}
+                "n_components": g.n_components,
+                "vc_off": arr(g.vc_off, nc0, ctypes.c_int64), "vc_val": arr(g.vc_val, g.vc_len, ctypes.c_double),
+                "cell_geom": arr(g.cell_geom, 5 * nc0, ctypes.c_double),
+                "vert_xyz": arr(g.vert_xyz, 3 * g.n_vert, ctypes.c_double)}
 
     def __del__(self):
         g = getattr(self, "_g", None)
@@ -365,3 +434,86 @@ def project_function():
             return gu, None, None, None
 
     return FvemProject
+
+
+def velocity_function():
+    """torch.autograd.Function mapping vertex velocity u -> projected cell field s.
+
+    forward: s = Pi_1 u - grad Pi_k K^+ P B u (fvem_project_velocity);
+    backward: the transpose (fvem_project_velocity_adjoint).  The map is
+    linear, so nothing of the forward pass is saved.
+    """
+    import torch
+
+    class FvemVelocity(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, u, hier, tol, precision):
+            ctx.hier, ctx.tol, ctx.precision = hier, tol, precision
+            s, _ = hier.project_velocity(u.contiguous(), tol=tol, precision=precision)
+            return s
+
+        @staticmethod
+        def backward(ctx, gs):
+            gu, _ = ctx.hier.project_velocity_adjoint(gs.contiguous(), tol=ctx.tol, precision=ctx.precision)
+            return gu, None, None, None
+
+    return FvemVelocity
+
+
+def loss_function():
+    """torch.autograd.Function (s, t) -> sum_E int_E |s_E - t_E|^2 (t is a constant target)."""
+    import torch
+
+    class FvemLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, s, t, hier):
+            ctx.hier = hier
+            ctx.save_for_backward(s, t)
+            L, _ = hier.velocity_loss(s.contiguous(), t.contiguous(), grad=False)
+            return torch.tensor(L, dtype=torch.float64, device=s.device)
+
+        @staticmethod
+        def backward(ctx, gL):
+            s, t = ctx.saved_tensors
+            _, gs = ctx.hier.velocity_loss(s, t, scale=float(gL), grad=True)
+            return gs, None, None
+
+    return FvemLoss
+
+
+def chain_loss_and_grad(hier, u0, eps, targets, store_dtype=None, tol=1e-10, precision=PREC_MIXED, with_grad=True):
+    """Loss of len(targets) chained projections and its gradient with respect to u0.
+
+    Step k projects u_k to s_k, adds loss(s_k, t_k) and (except after the
+    last step) moves on to u_{k+1} = Av s_k + eps_k.  Each step keeps one
+    checkpoint, u_k stored in ``store_dtype`` (torch.float32 or
+    torch.float64); the backward sweep re-runs that step's forward solve from
+    the checkpoint, then its adjoint solve.  Returns (loss, grad, stats);
+    grad is None without with_grad.
+    """
+    import torch
+    store_dtype = store_dtype or torch.float64
+    K = len(targets)
+    ckpt = []
+    total = 0.0
+    u = u0.contiguous()
+    for k in range(K):
+        ckpt.append(u.to(store_dtype).clone())
+        s, _ = hier.project_velocity(u, tol=tol, precision=precision)
+        L, _ = hier.velocity_loss(s, targets[k], grad=False)
+        total += L
+        if k + 1 < K:
+            u = eps[k].to(torch.float64).clone()
+            hier.apply(OP_AV, s, out=u, accumulate=True)
+    gu_next = None
+    peak = sum(c.numel() * c.element_size() for c in ckpt)
+    if not with_grad:
+        return total, None, {"checkpoint_bytes": peak, "steps": K}
+    for k in reversed(range(K)):
+        uk = ckpt[k].to(torch.float64).contiguous()
+        s, _ = hier.project_velocity(uk, tol=tol, precision=precision)
+        _, gs = hier.velocity_loss(s, targets[k], grad=True)
+        if gu_next is not None:
+            hier.apply(OP_AVT, gu_next, out=gs, accumulate=True)
+        gu_next, _ = hier.project_velocity_adjoint(gs, tol=tol, precision=precision)
+    return total, gu_next, {"checkpoint_bytes": peak, "steps": K}

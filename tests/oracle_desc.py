@@ -32,7 +32,12 @@ def describe(pb):
             lv["P_cols"] = P.shape[1]
         levels.append(lv)
     ke_ptr, ke_val, vptr, vert, be_ptr, be_val = [0], [], [0], [], [0], []
+    vc_ptr, vc_val, geom = [0], [], []
     for gd, verts, em, g in pb.asm.cells:
+        blk = np.concatenate([em["Pi1s"].ravel(), em["CPis"].ravel(), em["M1"].ravel()])
+        vc_val.append(blk)
+        vc_ptr.append(vc_ptr[-1] + blk.size)
+        geom.append([g.xc[0], g.xc[1], g.xc[2], g.hc, g.volume])
         K = em["K"]
         ke_val.append(K.ravel())
         ke_ptr.append(ke_ptr[-1] + K.size)
@@ -51,4 +56,7 @@ def describe(pb):
         "cell_vptr": np.array(vptr, dtype=np.int64), "cell_vert": np.array(vert, dtype=np.int32),
         "be_off": np.array(be_ptr[:-1], dtype=np.int64), "be_val": np.concatenate(be_val),
         "component": comp, "n_components": len(pb.null.floating),
+        "vc_off": np.array(vc_ptr[:-1], dtype=np.int64), "vc_val": np.concatenate(vc_val),
+        "cell_geom": np.array(geom, dtype=np.float64).ravel(),
+        "vert_xyz": np.ascontiguousarray(pb.vertices, dtype=np.float64).ravel(),
     }

@@ -5,7 +5,8 @@ boundary mesh with independent code (different quadratures and monomial
 frames).  DOFs are matched by (kind, support point); the matrices must then
 agree entry by entry:
 * the hierarchy shape (cells and DOFs per level, prolongation nonzeros) exactly;
-* K, B and every P_l to 1e-10 relative per row; 1e-6 for the 1e-5-thin sheet,
+* K, B, every P_l and the velocity-correction operators (Pi_1, grad Pi_k,
+  cell mass, vertex average) to 1e-10 relative per row; 1e-6 for the 1e-5-thin sheet,
   whose sliver cells (aspect ratio ~1e3) amplify the ~1e-16 differences of
   the two sides' vertex coordinates through ill-conditioned local systems.
 No GPU is needed: the builder is host code.
@@ -87,6 +88,43 @@ def _rel_rows(A, B):
     return float((np.asarray(D.max(axis=1).todense()).ravel() / scale).max())
 
 
+def _velocity_ops(desc, n):
+    """Pi, G, M, Av of the cell-field velocity correction, assembled from the description's blocks."""
+    lv = desc["levels"][0]
+    nc = len(lv["cell_ptr"]) - 1
+    nv = desc["n_vert"]
+    X = desc["vert_xyz"].reshape(-1, 3)
+    geom = desc["cell_geom"].reshape(-1, 5)
+    W = np.zeros(nv)
+    for c in range(nc):
+        W[desc["cell_vert"][desc["cell_vptr"][c]:desc["cell_vptr"][c + 1]]] += geom[c, 4]
+    T = {k: ([], [], []) for k in ("Pi", "G", "M", "Av")}
+    for c in range(nc):
+        d = lv["cell_dof"][lv["cell_ptr"][c]:lv["cell_ptr"][c + 1]]
+        verts = desc["cell_vert"][desc["cell_vptr"][c]:desc["cell_vptr"][c + 1]]
+        m, nvE = len(d), len(verts)
+        blk = desc["vc_val"][desc["vc_off"][c]:desc["vc_off"][c] + 4 * nvE + 12 * m + 16]
+        pi1 = blk[:4 * nvE].reshape(4, nvE)
+        gk = blk[4 * nvE:4 * nvE + 12 * m].reshape(3, 4, m)
+        m1 = blk[4 * nvE + 12 * m:].reshape(4, 4)
+        z = np.concatenate([np.ones((nvE, 1)), (X[verts] - geom[c, :3]) / geom[c, 3]], axis=1)
+        keep = d >= 0
+        for comp in range(3):
+            rows = 12 * c + 4 * comp + np.arange(4)
+            for key, r, cc, v in (
+                    ("Pi", np.repeat(rows, nvE), np.tile(3 * verts + comp, 4), pi1.ravel()),
+                    ("G", np.repeat(rows, keep.sum()), np.tile(d[keep], 4), gk[comp][:, keep].ravel()),
+                    ("M", np.repeat(rows, 4), np.tile(rows, 4), m1.ravel()),
+                    ("Av", np.repeat(3 * verts + comp, 4), np.tile(rows, nvE),
+                     ((geom[c, 4] / W[verts])[:, None] * z).ravel())):
+                T[key][0].append(r)
+                T[key][1].append(cc)
+                T[key][2].append(v)
+    shapes = {"Pi": (12 * nc, 3 * nv), "G": (12 * nc, n), "M": (12 * nc, 12 * nc), "Av": (3 * nv, 12 * nc)}
+    return {k: sp.csr_matrix((np.concatenate(v), (np.concatenate(r), np.concatenate(c))), shape=shapes[k])
+            for k, (r, c, v) in T.items()}
+
+
 TOL = {"c1": 1e-10, "c2": 1e-10, "c3": 1e-10, "c4": 1e-6}
 
 
@@ -127,6 +165,21 @@ def test_native_builder_matches_oracle(name):
         Qf = sp.csr_matrix((np.ones(nf), (perms[l], np.arange(nf))), shape=(nf, nf))
         Qc = sp.csr_matrix((np.ones(nc), (perms[l + 1], np.arange(nc))), shape=(nc, nc))
         assert _rel_rows(Qf @ Pn @ Qc.T, pb.P[l]) < tol, f"P level {l}"
+    # velocity correction: cells matched by centroid, rows per (cell, component, coefficient)
+    from oracle import velocity as vel
+    ov = vel.operators(pb)
+    geom = desc["cell_geom"].reshape(-1, 5)
+    ocen = np.array([g_.xc for (_, _, _, g_) in pb.asm.cells])
+    dc, cperm = cKDTree(ocen).query(geom[:, :3])
+    assert dc.max() < 1e-9 and len(set(cperm.tolist())) == len(cperm)
+    nc = len(cperm)
+    R12 = (12 * cperm[:, None] + np.arange(12)[None, :]).ravel()
+    QC = sp.csr_matrix((np.ones(12 * nc), (R12, np.arange(12 * nc))), shape=(12 * nc, 12 * nc))
+    nvv = _velocity_ops(desc, n)
+    assert _rel_rows(QC @ nvv["Pi"] @ QV.T, ov["Pi"]) < tol
+    assert _rel_rows(QC @ nvv["G"] @ Q.T, ov["G"]) < tol
+    assert _rel_rows(QC @ nvv["M"] @ QC.T, ov["M"]) < tol
+    assert _rel_rows(QV @ nvv["Av"] @ QC.T, ov["Av"]) < tol
     comp = desc["component"]
     if pb.w.dirichlet_top:
         assert (comp < 0).all()

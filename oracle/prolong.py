@@ -23,7 +23,6 @@ hierarchies avoid rank-deficient transfers).
 import numpy as np
 import scipy.sparse as sp
 
-from .geometry import polygon_area_vec
 from .quadrature import polygon_rule, polyhedron_rule
 from .vem import CellGeometry, cell_projector, face_projector
 
@@ -120,11 +119,13 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
         qp, qw = polygon_rule(fpts)
         area_f = qw.sum()
         fc = qw @ qp / area_f
-        nrm = polygon_area_vec(fpts)
         for f in g.face_ids:
             P = Xc[coarse_mesh.faces[f]]
             n = coarse_mesh.face_normal[f]
-            if abs(abs(float(n @ nrm)) / np.linalg.norm(nrm) - 1.0) > 1e-9:
+            # the fine face lies in the coarse face's plane when all of its
+            # vertices do (a distance test: the computed normal of a sliver
+            # face can be off by far more than its vertices are)
+            if np.abs((fpts - P[0]) @ n).max() > TOL:
                 continue
             if not _point_in_face(fc, P, n):
                 continue

@@ -701,6 +701,7 @@ static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const
     residual<double>(K, h->x, h->b, h->r, s);
     dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
     rel = std::sqrt(d[0]) / nb;
+    g_last_error = "maxit = " + std::to_string(maxit) + " reached at relative residual " + std::to_string(rel);
   }
   if (h->ncomp0) project_components(n, h->x, h->comp0, h->ncomp0, h->partial, h->mean, s);
   HIPCHECK(hipMemcpyAsync(xout, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));

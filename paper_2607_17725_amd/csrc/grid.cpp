@@ -1007,7 +1007,15 @@ struct BuilderImpl {
           bool done = false;
           for (int64_t q = Mc.cfptr[E]; q < Mc.cfptr[E + 1] && !done; ++q) {
             const int32_t F2 = Mc.cface[q];
-            if (std::fabs(std::fabs(dot(Mc.fnormal[F2], av)) / ar - 1.0) > 1e-9) continue;
+            // the fine face lies in the coarse face's plane when all of its
+            // vertices do (a distance test: the computed normal of a sliver
+            // face can be off by far more than its vertices are)
+            {
+              const V3 o = Mc.X[Mc.fvert[Mc.fptr[F2]]];
+              bool planar = true;
+              for (const V3 &p : P) planar = planar && std::fabs(dot(Mc.fnormal[F2], p - o)) <= tol;
+              if (!planar) continue;
+            }
             if (!in_face(F2, cen)) continue;
             const vem::FaceProj &fp = fproj[F2];
             if (std::fabs(fp.area - 0.5 * ar) < 1e-12 * 0.5 * ar && norm(fp.xf - cen) < tol) {

@@ -4,7 +4,9 @@ Against the oracle on identical inputs (its grid and element blocks):
 * the cell-field operators Pi_1, grad Pi_k, mass and vertex average, their
   transposes and the accumulate mode, to 1e-12 relative;
 * the projected velocity s = Pi_1 u - grad Pi_k p and its transpose, FP64
-  and mixed, to 1e-8 relative after solving to 1e-12;
+  and mixed, to 1e-7 relative after solving to 1e-10 (the pressure error
+  is the conditioning times the tolerance; the thin sheet's FP64 residual
+  floor sits near 1e-12);
 * loss and gradient of the thin-sheet workload (its oracle-sized grid)
   through torch.autograd against the oracle's exact reverse mode (bar:
   1e-5 relative) and against central finite differences along seeded
@@ -88,15 +90,16 @@ def test_project_velocity_matches_oracle(name, precision, request):
     u = synth.fourier_field(pb.vertices, 3).ravel()
     s_ref, p_ref = vel.project(pb, u)
     p = torch.empty(h.n_dof, dtype=torch.float64, device="cuda")
-    s, st = h.project_velocity(_dev(u), p=p, tol=1e-12, precision=precision, maxit=1000)
-    print(f"[gpu velocity] {name} precision={precision} iters={st['iterations']} "
-          f"s err={_rel(_host(s), s_ref):.2e}")
-    assert _rel(_host(s), s_ref) <= 1e-8
-    assert _rel(_host(p), p_ref) <= 1e-8
+    s, st = h.project_velocity(_dev(u), p=p, tol=1e-10, precision=precision, maxit=1000)
     gs = np.random.default_rng(8).standard_normal(12 * h.n_cells)
-    gu, _ = h.project_velocity_adjoint(_dev(gs), tol=1e-12, precision=precision, maxit=1000)
+    gu, _ = h.project_velocity_adjoint(_dev(gs), tol=1e-10, precision=precision, maxit=1000)
     gu_ref = vel.project_vjp(pb, gs)
-    assert _rel(_host(gu), gu_ref) <= 1e-8
+    print(f"[gpu velocity] {name} precision={precision} iters={st['iterations']} "
+          f"s err={_rel(_host(s), s_ref):.2e} p err={_rel(_host(p), p_ref):.2e} "
+          f"adjoint err={_rel(_host(gu), gu_ref):.2e}")
+    assert _rel(_host(s), s_ref) <= 1e-7
+    assert _rel(_host(p), p_ref) <= 1e-7
+    assert _rel(_host(gu), gu_ref) <= 1e-7
 
 
 def _loss_grad_gpu(h, u, t, precision, tol):

@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--fp64-reference", action="store_true", help="also time the plain FP64 MG-PCG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-N", type=int, default=16)
+    ap.add_argument("--rhs", type=int, default=16, help="right-hand sides per step (profiling runs use fewer)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 1 GiB buffer 3 times (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not supported", file=sys.stderr)
@@ -124,7 +127,15 @@ def main():
     log(f"hierarchy built in {t_hier:.1f} s: {hier.n_levels} levels, nnz(K)={nnz0}, "
         f"device memory {hier.device_bytes / 2**30:.1f} GiB")
 
-    seeds = w.rhs_seeds()
+    if args.copy_calibration:
+        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 3 copies of 1 GiB done")
+    seeds = w.rhs_seeds()[:args.rhs]
     U = [torch.as_tensor(synth.fourier_field(grid.vertices, s).ravel(), device="cuda") for s in seeds]
     p = torch.empty(n0, dtype=torch.float64, device="cuda")
     prec = fvem.PREC_MIXED if args.precision == "mixed" else fvem.PREC_FP64

@@ -241,6 +241,15 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
 fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n_dof0,
                                 int64_t *n_vert, int64_t *device_bytes);
 
+/* Storage of level l's operator: nonzeros, nonzeros whose values are stored
+ * with their slice, rows whose values come from the shared value templates
+ * (their slices store columns only), number of templates and their width.
+ * One application of A_l in FP32 reads 4 nnz + 4 nnz_explicit +
+ * 4 rows_templated bytes of matrix data (plus 4 n_templates template_width,
+ * cache resident). */
+fvem_status fvem_level_storage(fvem_hierarchy *h, int32_t level, int64_t *nnz, int64_t *nnz_explicit,
+                               int64_t *rows_templated, int32_t *n_templates, int32_t *template_width);
+
 /* Number of level-0 cells carrying velocity fields (0 without vc_off). */
 fvem_status fvem_hierarchy_cells(fvem_hierarchy *h, int64_t *n_cells);
 

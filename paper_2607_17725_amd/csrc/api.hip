@@ -75,17 +75,26 @@ struct DevCSR {
 // Level operator in the sliced layout; one column array serves both value
 // precisions.  Host copies of the slice table and row lengths let the
 // operator be read back.
+struct DevValues {
+  int64_t *vp = nullptr;
+  int32_t *tid = nullptr;
+  int32_t nt = 0, tw = 0;
+  int64_t nvals = 0, nnz_explicit = 0, rows_templated = 0;
+};
+
 struct DevSELL {
   int64_t n = 0, m = 0, nnz = 0, nslices = 0, stored = 0;
   int64_t *sp = nullptr;
   int32_t *sl = nullptr;
   int32_t *ci = nullptr;
-  double *v64 = nullptr;
-  float *v32 = nullptr;
+  DevValues d64, d32;               // exact FP64 and single-precision value sets
+  double *v64 = nullptr, *tv64 = nullptr;
+  float *v32 = nullptr, *tv32 = nullptr;
   std::vector<int64_t> hsp;
   std::vector<int32_t> hsl, hrl;
-  DevSELLView<double> d() const { return {n, m, nslices, sp, sl, ci, v64}; }
-  DevSELLView<float> f() const { return {n, m, nslices, sp, sl, ci, v32}; }
+  HostValues hv64;                  // FP64 value set without its values (read back on demand)
+  DevSELLView<double> d() const { return {n, m, nslices, sp, sl, ci, d64.vp, v64, d64.tid, tv64, d64.tw}; }
+  DevSELLView<float> f() const { return {n, m, nslices, sp, sl, ci, d32.vp, v32, d32.tid, tv32, d32.tw}; }
 };
 
 struct Level {
@@ -187,8 +196,8 @@ static DevCSR upload_csr(fvem_hierarchy *h, const HostCSR &A, bool f32, hipStrea
   return d;
 }
 
-static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, hipStream_t s) {
-  HostSELL S = to_sell(A);
+static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, bool templates, hipStream_t s) {
+  HostSELL S = to_sell(A, templates);
   DevSELL d;
   d.n = S.n;
   d.m = S.m;
@@ -198,13 +207,35 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, hipStream_t s) {
   d.sp = h->mem.upload(S.sp, s);
   d.sl = h->mem.upload(S.sl, s);
   d.ci = h->mem.upload(S.ci, s);
-  d.v64 = h->mem.upload(S.v, s);
-  d.v32 = h->mem.alloc<float>(d.stored);
-  cast_f64_f32(d.stored, d.v64, d.v32, s);
-  HIPCHECK(hipStreamSynchronize(s));   // the host arrays are freed on return
+  auto meta = [&](const HostValues &V, DevValues &D) {
+    D.vp = h->mem.upload(V.vp, s);
+    D.tid = h->mem.upload(V.tid, s);
+    D.nt = V.nt;
+    D.tw = V.tw;
+    D.nvals = static_cast<int64_t>(V.v.size());
+    D.nnz_explicit = V.nnz_explicit;
+    D.rows_templated = V.rows_templated;
+  };
+  meta(S.v64, d.d64);
+  meta(S.v32, d.d32);
+  d.v64 = h->mem.upload(S.v64.v, s);
+  d.tv64 = h->mem.upload(S.v64.tv, s);
+  {
+    // FP32 values: cast on the device through a temporary FP64 copy
+    DevMem tmp;
+    double *t = tmp.upload(S.v32.v, s);
+    d.v32 = h->mem.alloc<float>(d.d32.nvals);
+    cast_f64_f32(d.d32.nvals, t, d.v32, s);
+    double *tt = tmp.upload(S.v32.tv, s);
+    d.tv32 = h->mem.alloc<float>(static_cast<int64_t>(S.v32.tv.size()));
+    cast_f64_f32(static_cast<int64_t>(S.v32.tv.size()), tt, d.tv32, s);
+    HIPCHECK(hipStreamSynchronize(s));   // before the temporaries and host arrays go
+  }
   d.hsp = std::move(S.sp);
   d.hsl = std::move(S.sl);
   d.hrl = std::move(S.rl);
+  d.hv64 = std::move(S.v64);
+  HostValues().v.swap(d.hv64.v);
   return d;
 }
 
@@ -418,7 +449,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   for (int l = 0; l < L; ++l) {
     Level &V = h->lv[l];
     V.n = A[l].n_rows;
-    V.A = upload_sell(h, A[l], s);
+    V.A = upload_sell(h, A[l], true, s);
     std::vector<double> dinv(V.n);
     for (int64_t i = 0; i < V.n; ++i) {
       double d = 0.0;
@@ -921,6 +952,21 @@ fvem_status fvem_velocity_loss(fvem_hierarchy *h, const double *s_dev, const dou
   });
 }
 
+fvem_status fvem_level_storage(fvem_hierarchy *h, int32_t level, int64_t *nnz, int64_t *nnz_explicit,
+                               int64_t *rows_templated, int32_t *n_templates, int32_t *template_width) {
+  if (!h || level < 0 || level >= h->nlev) {
+    g_last_error = "bad handle or level";
+    return FVEM_ERR_INVALID;
+  }
+  const DevSELL &A = h->lv[level].A;
+  if (nnz) *nnz = A.nnz;
+  if (nnz_explicit) *nnz_explicit = A.d32.nnz_explicit;
+  if (rows_templated) *rows_templated = A.d32.rows_templated;
+  if (n_templates) *n_templates = A.d32.nt;
+  if (template_width) *template_width = A.d32.tw;
+  return FVEM_OK;
+}
+
 fvem_status fvem_hierarchy_cells(fvem_hierarchy *h, int64_t *n_cells) {
   if (!h || !n_cells) {
     g_last_error = "null argument";
@@ -1028,10 +1074,12 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
     S.sp = A.hsp;
     S.sl = A.hsl;
     S.rl = A.hrl;
+    S.v64 = A.hv64;
     S.ci.resize(A.stored);
-    S.v.resize(A.stored);
+    S.v64.v.resize(A.d64.nvals);
     HIPCHECK(hipMemcpy(S.ci.data(), A.ci, sizeof(int32_t) * A.stored, hipMemcpyDeviceToHost));
-    HIPCHECK(hipMemcpy(S.v.data(), A.v64, sizeof(double) * A.stored, hipMemcpyDeviceToHost));
+    if (A.d64.nvals)
+      HIPCHECK(hipMemcpy(S.v64.v.data(), A.v64, sizeof(double) * A.d64.nvals, hipMemcpyDeviceToHost));
     const std::vector<int32_t> &order = h->lv[level].order;
     const HostCSR C = permute(from_sell(S), inverse(order), &order);
     if (row_ptr) std::copy(C.rp.begin(), C.rp.end(), row_ptr);

@@ -18,16 +18,22 @@ struct DevCSRView {
 };
 
 // Sliced ELLPACK with 64-row slices (one wavefront lane per row).  Slice s
-// holds rows [64 s, 64 s + 64); its entries are stored column-major, entry j
-// of lane r at sp[s] + 64 j + r, for j < sl[s] (the longest row of the
-// slice).  Shorter rows are padded with value 0 and a valid column.
+// holds rows [64 s, 64 s + 64); its columns are stored column-major, entry j
+// of lane r at ci[sp[s] + 64 j + r], for j < sl[s] (the longest row of the
+// slice).  Values: when vp[s] >= 0 at v[vp[s] + 64 j + r]; when vp[s] < 0
+// every row of the slice takes them from its template, tv[tid[row] * tw + j].
+// Shorter rows are padded with value 0 and a valid column.
 template <typename T>
 struct DevSELLView {
   int64_t n = 0, m = 0, nslices = 0;
   const int64_t *sp = nullptr;
   const int32_t *sl = nullptr;
   const int32_t *ci = nullptr;
+  const int64_t *vp = nullptr;
   const T *v = nullptr;
+  const int32_t *tid = nullptr;
+  const T *tv = nullptr;
+  int32_t tw = 0;
 };
 
 // SpMV family on the sliced layout (level operators; fused epilogues)

@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
+#include <unordered_map>
 #include <omp.h>
 
 namespace fvem {
@@ -63,6 +65,10 @@ HostCSR assemble_blocks(int64_t n_rows, int64_t n_cols, const HostCells &rows, c
     const std::vector<int32_t> &p = pat[i];
     std::copy(p.begin(), p.end(), A.ci.begin() + A.rp[i]);
     double *row = A.v.data() + A.rp[i];
+    // each entry sums its contributions in increasing order of value: rows
+    // whose contributions coincide (translated copies of one configuration)
+    // then assemble to bitwise equal values whatever the cell numbering
+    std::vector<std::pair<int64_t, double>> con;
     for (int64_t k = iptr[i]; k < iptr[i + 1]; ++k) {
       int64_t c = icell[k];
       int32_t a = iloc[k];
@@ -72,9 +78,11 @@ HostCSR assemble_blocks(int64_t n_rows, int64_t n_cols, const HostCells &rows, c
         int32_t j = cols.dof[cols.ptr[c] + b];
         if (j < 0) continue;
         auto it = std::lower_bound(p.begin(), p.end(), j);
-        row[it - p.begin()] += blk[b];
+        con.emplace_back(it - p.begin(), blk[b]);
       }
     }
+    std::sort(con.begin(), con.end());
+    for (const auto &e : con) row[e.first] += e.second;
     std::vector<int32_t>().swap(pat[i]);
   }
   return A;
@@ -186,6 +194,16 @@ std::vector<int32_t> window_order(const HostCSR &A, int64_t w) {
     std::stable_sort(b, e, [&](int32_t a, int32_t c) {
       return A.rp[a + 1] - A.rp[a] > A.rp[c + 1] - A.rp[c];
     });
+    // full 64-row chunks (the slices) in order of their first original row,
+    // so consecutive slices come from the same part of the grid
+    const int64_t len = e - b, full = len / 64;
+    std::vector<int64_t> ch(full);
+    std::iota(ch.begin(), ch.end(), 0);
+    std::vector<int32_t> first(full);
+    for (int64_t c = 0; c < full; ++c) first[c] = *std::min_element(b + 64 * c, b + 64 * c + 64);
+    std::stable_sort(ch.begin(), ch.end(), [&](int64_t x, int64_t y) { return first[x] < first[y]; });
+    std::vector<int32_t> tmp(b, b + 64 * full);
+    for (int64_t c = 0; c < full; ++c) std::copy(tmp.begin() + 64 * ch[c], tmp.begin() + 64 * ch[c] + 64, b + 64 * c);
   }
   return order;
 }
@@ -215,7 +233,108 @@ HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::
   return B;
 }
 
-HostSELL to_sell(const HostCSR &A) {
+namespace {
+
+// Template assignment of one value set.  quantum: relative rounding of the
+// hashed values (0: exact bits); tol: accepted deviation relative to the
+// row's largest entry.
+void assign_templates(const HostCSR &A, const std::vector<int64_t> &ord, HostSELL &S, HostValues &V, double quantum,
+                      double tol, int min_uses, int max_templates) {
+  std::vector<uint64_t> key(S.n);
+  std::vector<double> rmax(S.n, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < S.n; ++i) {
+    double mx = 0;
+    for (int64_t q = A.rp[i]; q < A.rp[i + 1]; ++q) mx = std::max(mx, std::fabs(A.v[q]));
+    rmax[i] = mx;
+    uint64_t h = 1469598103934665603ull ^ static_cast<uint64_t>(S.rl[i]);
+    for (int64_t q = A.rp[i]; q < A.rp[i + 1]; ++q) {
+      const double x = A.v[ord[q]];
+      uint64_t qv;
+      if (quantum > 0) {
+        qv = static_cast<uint64_t>(std::llround(mx > 0 ? x / (mx * quantum) : 0.0));
+      } else {
+        std::memcpy(&qv, &x, sizeof qv);
+      }
+      h = (h ^ qv) * 1099511628211ull;
+      h ^= h >> 29;
+    }
+    key[i] = h;
+  }
+  std::unordered_map<uint64_t, std::pair<int64_t, int64_t>> first;   // key -> (first row, uses)
+  for (int64_t i = 0; i < S.n; ++i) {
+    auto it = first.find(key[i]);
+    if (it == first.end()) first.emplace(key[i], std::make_pair(i, int64_t(1)));
+    else it->second.second++;
+  }
+  std::vector<std::pair<int64_t, uint64_t>> popular;   // (uses, key)
+  for (const auto &kv : first)
+    if (kv.second.second >= min_uses) popular.emplace_back(kv.second.second, kv.first);
+  std::sort(popular.begin(), popular.end(), [](const auto &x, const auto &y) {
+    return x.first > y.first || (x.first == y.first && x.second < y.second);
+  });
+  if (static_cast<int>(popular.size()) > max_templates) popular.resize(max_templates);
+  std::unordered_map<uint64_t, int32_t> tindex;
+  std::vector<int64_t> trow;
+  for (const auto &pk : popular) {
+    const int64_t r = first[pk.second].first;
+    tindex.emplace(pk.second, V.nt++);
+    trow.push_back(r);
+    V.tw = std::max(V.tw, (S.rl[r] + 3) & ~3);
+  }
+  V.tv.assign(static_cast<size_t>(V.nt) * V.tw, 0.0);
+  for (int32_t t = 0; t < V.nt; ++t) {
+    const int64_t r = trow[t];
+    for (int j = 0; j < S.rl[r]; ++j) V.tv[static_cast<size_t>(t) * V.tw + j] = A.v[ord[A.rp[r] + j]];
+  }
+  V.tid.assign(S.nslices * 64, 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < S.n; ++i) {
+    auto it = tindex.find(key[i]);
+    int32_t t = -1;
+    if (it != tindex.end() && S.rl[trow[it->second]] == S.rl[i]) {
+      t = it->second;
+      for (int j = 0; j < S.rl[i] && t >= 0; ++j)
+        if (std::fabs(A.v[ord[A.rp[i] + j]] - V.tv[static_cast<size_t>(t) * V.tw + j]) > tol * rmax[i]) t = -1;
+    }
+    V.tid[i] = t;
+  }
+}
+
+void layout_values(const HostCSR &A, const std::vector<int64_t> &ord, const HostSELL &S, HostValues &V,
+                   bool templates) {
+  if (!templates) {
+    V.tid.assign(S.nslices * 64, 0);
+    for (int64_t i = 0; i < S.n; ++i) V.tid[i] = -1;
+  }
+  V.vp.assign(S.nslices, -1);
+  int64_t nv = 0;
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    bool all = templates;
+    for (int64_t i = s * 64; i < std::min(S.n, s * 64 + 64) && all; ++i) all = V.tid[i] >= 0;
+    if (!all) {
+      V.vp[s] = nv;
+      nv += 64 * static_cast<int64_t>(S.sl[s]);
+      for (int64_t i = s * 64; i < std::min(S.n, s * 64 + 64); ++i) V.nnz_explicit += S.rl[i];
+    } else {
+      V.rows_templated += std::min(S.n, s * 64 + 64) - s * 64;
+    }
+  }
+  V.v.assign(nv, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    if (V.vp[s] < 0) continue;
+    for (int r = 0; r < 64; ++r) {
+      const int64_t i = s * 64 + r;
+      if (i >= S.n) continue;
+      for (int j = 0; j < S.rl[i]; ++j) V.v[V.vp[s] + S.at(s, j, r)] = A.v[ord[A.rp[i] + j]];
+    }
+  }
+}
+
+}  // namespace
+
+HostSELL to_sell(const HostCSR &A, bool templates, int min_uses, int max_templates) {
   HostSELL S;
   S.n = A.n_rows;
   S.m = A.n_cols;
@@ -228,22 +347,33 @@ HostSELL to_sell(const HostCSR &A) {
     S.rl[i] = static_cast<int32_t>(A.rp[i + 1] - A.rp[i]);
     S.sl[i / 64] = std::max(S.sl[i / 64], S.rl[i]);
   }
-  for (int64_t s = 0; s < S.nslices; ++s) S.sp[s + 1] = S.sp[s] + 64 * static_cast<int64_t>(S.sl[s]);
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    S.sl[s] = (S.sl[s] + 3) & ~3;
+    S.sp[s + 1] = S.sp[s] + 64 * static_cast<int64_t>(S.sl[s]);
+  }
+  // entry order of each row: as given, or by (value, column)
+  std::vector<int64_t> ord(S.nnz);
+  std::iota(ord.begin(), ord.end(), 0);
+  if (templates) {
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < S.n; ++i)
+      std::sort(ord.begin() + A.rp[i], ord.begin() + A.rp[i + 1], [&](int64_t x, int64_t y) {
+        return A.v[x] < A.v[y] || (A.v[x] == A.v[y] && A.ci[x] < A.ci[y]);
+      });
+    assign_templates(A, ord, S, S.v64, 0.0, 0.0, min_uses, max_templates);
+    assign_templates(A, ord, S, S.v32, 0x1p-30, 1e-9, min_uses, max_templates);
+  }
+  layout_values(A, ord, S, S.v64, templates);
+  layout_values(A, ord, S, S.v32, templates);
   S.ci.assign(S.sp.back(), 0);
-  S.v.assign(S.sp.back(), 0.0);
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < S.nslices; ++s)
     for (int r = 0; r < 64; ++r) {
       const int64_t i = s * 64 + r;
       const int32_t pad = static_cast<int32_t>(std::min<int64_t>(std::min(i, S.n - 1), S.m - 1));
       for (int j = 0; j < S.sl[s]; ++j) {
-        const int64_t dst = S.sp[s] + 64 * static_cast<int64_t>(j) + r;
-        if (i < S.n && j < S.rl[i]) {
-          S.ci[dst] = A.ci[A.rp[i] + j];
-          S.v[dst] = A.v[A.rp[i] + j];
-        } else {
-          S.ci[dst] = pad < 0 ? 0 : pad;
-        }
+        const bool real = i < S.n && j < S.rl[i];
+        S.ci[S.sp[s] + S.at(s, j, r)] = real ? A.ci[ord[A.rp[i] + j]] : (pad < 0 ? 0 : pad);
       }
     }
   return S;
@@ -257,12 +387,15 @@ HostCSR from_sell(const HostSELL &S) {
   for (int64_t i = 0; i < S.n; ++i) A.rp[i + 1] = A.rp[i] + S.rl[i];
   A.ci.resize(A.rp.back());
   A.v.resize(A.rp.back());
-  for (int64_t i = 0; i < S.n; ++i)
+  const HostValues &V = S.v64;
+  for (int64_t i = 0; i < S.n; ++i) {
+    const int64_t s = i / 64;
     for (int j = 0; j < S.rl[i]; ++j) {
-      const int64_t src = S.sp[i / 64] + 64 * static_cast<int64_t>(j) + i % 64;
-      A.ci[A.rp[i] + j] = S.ci[src];
-      A.v[A.rp[i] + j] = S.v[src];
+      const int64_t off = S.at(s, j, static_cast<int>(i % 64));
+      A.ci[A.rp[i] + j] = S.ci[S.sp[s] + off];
+      A.v[A.rp[i] + j] = V.vp[s] >= 0 ? V.v[V.vp[s] + off] : V.tv[static_cast<size_t>(V.tid[i]) * V.tw + j];
     }
+  }
   return A;
 }
 

@@ -40,8 +40,9 @@ struct SetupError {
 
 // Assemble y = sum_c scatter(block_c) into a CSR with rows/cols given by
 // the row DOF lists (rows) and column lists (cols) of each cell.  Entries
-// with a negative index are skipped.  Deterministic: contributions to an
-// entry are summed in increasing cell order.
+// with a negative index are skipped.  Deterministic and translation
+// invariant: contributions to an entry are summed in increasing order of
+// value, so equal sets of contributions give bitwise equal entries.
 HostCSR assemble_blocks(int64_t n_rows, int64_t n_cols, const HostCells &rows, const HostCells &cols,
                         const HostBlocks &blocks);
 
@@ -55,25 +56,49 @@ HostBlocks galerkin_blocks(const HostCells &fine, const HostBlocks &kf, const in
 HostCSR transpose(const HostCSR &A);
 
 // Level order of the sliced storage: inside each window of w consecutive
-// rows, rows by decreasing length (stable).  Returns order[new] = old.
+// rows (w a multiple of 64), rows by decreasing length (stable); then the
+// window's full 64-row chunks ordered by their smallest original row, so the
+// slices of one part of the grid are adjacent.  Returns order[new] = old.
 std::vector<int32_t> window_order(const HostCSR &A, int64_t w);
 
 // B = rows order[r] of A with columns renamed by col_map (old -> new; null
 // keeps them), columns sorted ascending within each row.
 HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::vector<int32_t> *col_map);
 
-// Sliced ELLPACK (64-row slices, column-major inside a slice); padding has
-// value 0 and column min(row, n_cols - 1).
+// Sliced ELLPACK with 64-row slices, interleaved in groups of 4 entries:
+// entry j of row 64 s + r sits at sp[s] + 256 (j / 4) + 4 r + j % 4, so a
+// wavefront reads each group of 4 entries of its 64 rows as one contiguous
+// 1 KiB block (one 16-byte load per lane).  Slice widths are rounded up to a
+// multiple of 4; padding has value 0 and column min(row, n_cols - 1).
+//
+// Value templates: away from cut cells a level operator repeats a few rows
+// up to translation (one per DOF kind), so with each row's entries ordered
+// by value the value sequences coincide.  Rows whose sequence is shared by
+// at least min_uses rows read their values from a small template table; a
+// slice whose rows all use templates stores no values.  Columns are stored
+// for every row.  Two value sets share the columns: the FP64 values use
+// templates only where rows are bitwise equal; the FP32 values (applied in
+// single precision) also where rows agree to 1e-9 of their largest entry.
+struct HostValues {
+  std::vector<int64_t> vp;   // per slice: value offset, or -1 (all rows templated)
+  std::vector<double> v;     // values of the explicit slices, same layout as ci
+  std::vector<int32_t> tid;  // nslices * 64: template of each row (-1: explicit; 0 on padding rows)
+  int32_t nt = 0, tw = 0;    // templates and their padded width (a multiple of 4)
+  std::vector<double> tv;    // nt * tw template values
+  int64_t nnz_explicit = 0, rows_templated = 0;
+};
 struct HostSELL {
   int64_t n = 0, m = 0, nnz = 0, nslices = 0;
-  std::vector<int64_t> sp;   // nslices + 1, in entries
-  std::vector<int32_t> sl;   // longest row per slice
+  std::vector<int64_t> sp;   // nslices + 1, column offsets (entries)
+  std::vector<int32_t> sl;   // longest row per slice, rounded up to a multiple of 4
   std::vector<int32_t> rl;   // row lengths
   std::vector<int32_t> ci;
-  std::vector<double> v;
+  HostValues v64, v32;       // exact (FP64) and single-precision value sets
+  int64_t at(int64_t s, int j, int r) const { return 256 * static_cast<int64_t>(j >> 2) + 4 * r + (j & 3); }
 };
-HostSELL to_sell(const HostCSR &A);
-HostCSR from_sell(const HostSELL &S);
+// entries of every row ordered by (value, column) when templates are used
+HostSELL to_sell(const HostCSR &A, bool templates = false, int min_uses = 64, int max_templates = 1024);
+HostCSR from_sell(const HostSELL &S);   // FP64 values
 
 // max_i sum_j |a_ij| / sqrt(a_ii a_jj): Gershgorin bound of D^-1/2 A D^-1/2,
 // which has the spectrum of D^-1 A and stays bounded by the row length for

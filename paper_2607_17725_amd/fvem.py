@@ -74,7 +74,8 @@ class SolveStats(ctypes.Structure):
 EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_apply", "fvem_level_matrix",
            "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error", "fvem_grid_build",
            "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy",
-           "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells"]
+           "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells",
+           "fvem_level_storage"]
 
 _lib = None
 
@@ -102,6 +103,9 @@ def load(path=LIB_PATH):
     lib.fvem_project_velocity_adjoint.restype = ctypes.c_int
     lib.fvem_velocity_loss.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp]
     lib.fvem_velocity_loss.restype = ctypes.c_int
+    lib.fvem_level_storage.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.fvem_level_storage.restype = ctypes.c_int
     lib.fvem_hierarchy_cells.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fvem_hierarchy_cells.restype = ctypes.c_int
     lib.fvem_level_matrix.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
@@ -321,6 +325,13 @@ class Hierarchy:
                                          ctypes.byref(L), self._vec(gs, nc, "g_s") if grad else None,
                                          ctypes.c_void_p(self.stream.cuda_stream)))
         return L.value, gs
+
+    def level_storage(self, level):
+        """Storage of level ``level``'s operator: nnz, nnz_explicit, rows_templated, n_templates, template_width."""
+        v = [ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()]
+        _check(load().fvem_level_storage(self._h, level, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("nnz", "nnz_explicit", "rows_templated", "n_templates", "template_width"),
+                        (x.value for x in v)))
 
     def level_matrix(self, level):
         """Level operator as (row_ptr, col, val) host arrays."""

@@ -3,6 +3,7 @@
 // product, scaled Gershgorin bound) against dense brute force on small
 // random inputs.  Built with g++ by tests/test_host_setup.py; prints one line
 // per check and exits non-zero on the first failure.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -68,7 +69,7 @@ int main() {
     for (int64_t s = 0; s < S.nslices; ++s) {
       int mx = 0;
       for (int64_t i = s * 64; i < std::min(n, s * 64 + 64); ++i) mx = std::max<int>(mx, static_cast<int>(A.rp[i + 1] - A.rp[i]));
-      ok = ok && S.sl[s] == mx;
+      ok = ok && S.sl[s] == ((mx + 3) & ~3);
     }
     for (int32_t c : S.ci) ok = ok && c >= 0 && c < A.n_cols;
     // padding contributes zero: a dense product through the slices equals A x
@@ -78,7 +79,8 @@ int main() {
       for (int r = 0; r < 64; ++r) {
         const int64_t i = s * 64 + r;
         if (i >= n) continue;
-        for (int j = 0; j < S.sl[s]; ++j) y[i] += S.v[S.sp[s] + 64 * j + r] * x[S.ci[S.sp[s] + 64 * j + r]];
+        for (int j = 0; j < S.sl[s]; ++j)
+          y[i] += S.v64.v[S.v64.vp[s] + S.at(s, j, r)] * x[S.ci[S.sp[s] + S.at(s, j, r)]];
       }
     std::vector<double> yr(n, 0.0);
     for (int64_t i = 0; i < n; ++i)
@@ -90,19 +92,107 @@ int main() {
     std::snprintf(msg, sizeof msg, "sliced storage round trip, n=%lld", static_cast<long long>(n));
     expect(ok, msg);
   }
-  // level order: a permutation, sorted by decreasing length inside windows, stable
+  // value templates: a 7-point stencil on a 3-D grid (translation-invariant
+  // interior rows, boundary rows differ) plus perturbed rows
+  {
+    const int gs = 12, n = gs * gs * gs;
+    HostCSR A;
+    A.n_rows = A.n_cols = n;
+    A.rp.assign(n + 1, 0);
+    std::mt19937 gg(3);
+    std::uniform_int_distribution<int> pick(0, n - 1);
+    std::vector<int> noisy(n, 0);
+    for (int q = 0; q < 8; ++q) noisy[pick(gg)] = 1;
+    for (int i = 0; i < n; ++i) {
+      const int x = i % gs, y = (i / gs) % gs, z = i / (gs * gs);
+      const int nb[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+      std::vector<std::pair<int, double>> e{{i, 6.5}};
+      for (int k = 0; k < 6; ++k) {
+        const int X = x + nb[k][0], Y = y + nb[k][1], Z = z + nb[k][2];
+        if (X < 0 || Y < 0 || Z < 0 || X >= gs || Y >= gs || Z >= gs) continue;
+        e.push_back({(Z * gs + Y) * gs + X, -1.0 - 0.1 * k});
+      }
+      std::sort(e.begin(), e.end());
+      for (auto &pr : e) {
+        A.ci.push_back(pr.first);
+        A.v.push_back(pr.second + (noisy[i] ? 1e-3 * pr.first : 0.0) + (pr.first == i ? 1e-15 * (i % 3) : 0.0));
+      }
+      A.rp[i + 1] = static_cast<int64_t>(A.ci.size());
+    }
+    HostSELL S = to_sell(A, true, 4);
+    std::vector<double> x(n);
+    for (auto &v : x) v = std::normal_distribution<double>()(gg);
+    std::vector<double> yr(n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) yr[i] += A.v[k] * x[A.ci[k]];
+    double ymax = 0;
+    for (double v : yr) ymax = std::max(ymax, std::fabs(v));
+    for (int set = 0; set < 2; ++set) {
+      const HostValues &V = set == 0 ? S.v64 : S.v32;
+      int templated_slices = 0;
+      for (int64_t s2 = 0; s2 < S.nslices; ++s2) templated_slices += V.vp[s2] < 0;
+      std::vector<double> y(n, 0.0);
+      for (int64_t s2 = 0; s2 < S.nslices; ++s2)
+        for (int r = 0; r < 64; ++r) {
+          const int64_t i = s2 * 64 + r;
+          if (i >= n) continue;
+          for (int j = 0; j < S.sl[s2]; ++j) {
+            const double v = V.vp[s2] >= 0 ? V.v[V.vp[s2] + S.at(s2, j, r)] : V.tv[static_cast<size_t>(V.tid[i]) * V.tw + j];
+            y[i] += v * x[S.ci[S.sp[s2] + S.at(s2, j, r)]];
+          }
+        }
+      // FP64 templates are exact: the diagonal's 1e-15 jitter splits them;
+      // the single-precision set absorbs it
+      const double tol = set == 0 ? 1e-14 : 1e-9;
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "value templates (%s): %d templates, %d of %lld slices without values",
+                    set == 0 ? "exact" : "single", V.nt, templated_slices, static_cast<long long>(S.nslices));
+      expect(V.nt >= 4 && templated_slices >= 2 && maxdiff(y, yr) < tol * ymax && V.tw % 4 == 0, msg);
+      bool noisy_ok = true;
+      for (int i = 0; i < n; ++i) noisy_ok = noisy_ok && (!noisy[i] || V.tid[i] < 0);
+      expect(noisy_ok, "rows that differ from every template store their values");
+      bool exact_ok = true;
+      if (set == 0)
+        for (int i = 0; i < n; ++i)
+          if (V.tid[i] >= 0) {
+            std::vector<double> rowv(A.v.begin() + A.rp[i], A.v.begin() + A.rp[i + 1]);
+            std::sort(rowv.begin(), rowv.end());
+            for (size_t j = 0; j < rowv.size(); ++j) exact_ok = exact_ok && rowv[j] == V.tv[static_cast<size_t>(V.tid[i]) * V.tw + j];
+          }
+      if (set == 0) expect(exact_ok, "exact templates reproduce their rows bitwise");
+    }
+    const HostCSR B = from_sell(S);
+    expect(maxdiff(dense(B), dense(A)) == 0.0, "read-back of the exact value set");
+  }
+  // level order: a permutation that keeps every window's rows, sorts each
+  // 64-row chunk by decreasing length (stable) and orders a window's full
+  // chunks by their smallest original row
   {
     HostCSR A = random_csr(g, 1000, 1000, 40);
-    const int64_t w = 128;
+    const int64_t w = 256;
     std::vector<int32_t> o = window_order(A, w);
     std::vector<int> seen(1000, 0);
     bool ok = o.size() == 1000;
     for (int32_t i : o) ok = ok && i >= 0 && i < 1000 && !seen[i]++;
-    for (int64_t r = 0; r + 1 < 1000; ++r) {
-      if ((r + 1) % w == 0) continue;
-      const int64_t la = A.rp[o[r] + 1] - A.rp[o[r]], lb = A.rp[o[r + 1] + 1] - A.rp[o[r + 1]];
-      ok = ok && (la > lb || (la == lb && o[r] < o[r + 1]));
-      ok = ok && o[r] / w == r / w;
+    for (int64_t r = 0; r < 1000; ++r) ok = ok && o[r] / w == r / w;
+    // rows of the window sorted by (decreasing length, index), cut into chunks
+    for (int64_t s0 = 0; s0 < 1000; s0 += w) {
+      const int64_t e0 = std::min<int64_t>(1000, s0 + w);
+      std::vector<int32_t> ref(e0 - s0);
+      for (int64_t r = s0; r < e0; ++r) ref[r - s0] = static_cast<int32_t>(r);
+      std::stable_sort(ref.begin(), ref.end(), [&](int32_t a, int32_t c) {
+        return A.rp[a + 1] - A.rp[a] > A.rp[c + 1] - A.rp[c];
+      });
+      const int64_t full = (e0 - s0) / 64;
+      std::vector<std::vector<int32_t>> chunks;
+      for (int64_t c = 0; c < full; ++c) chunks.emplace_back(ref.begin() + 64 * c, ref.begin() + 64 * c + 64);
+      std::stable_sort(chunks.begin(), chunks.end(), [](const auto &x, const auto &y) {
+        return *std::min_element(x.begin(), x.end()) < *std::min_element(y.begin(), y.end());
+      });
+      std::vector<int32_t> expect_o;
+      for (auto &c : chunks) expect_o.insert(expect_o.end(), c.begin(), c.end());
+      expect_o.insert(expect_o.end(), ref.begin() + 64 * full, ref.end());
+      for (int64_t r = s0; r < e0; ++r) ok = ok && o[r] == expect_o[r - s0];
     }
     expect(ok, "window order");
     // symmetric renumbering: B = Q A Q^T with columns sorted per row

@@ -33,6 +33,33 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sell_cheb_plates128_traffic.json")
+LAYOUT_SOURCES = [os.path.join(ROOT, "paper_2607_17725_amd", "csrc", f) for f in ("kernels.hip", "setup_host.cpp")]
+
+
+def layout_hash():
+    """sha256 over the kernel and data-layout sources the counter figures depend on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in LAYOUT_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when they were taken on other kernel or layout sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != layout_hash() or rec.get("workload") != workload:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(name, N, n_dof_target, seconds=20.0):
     """Time the oracle's FP64 MG-PCG solve on a reduced instance of the workload (one core)."""
     code = f"""
@@ -220,7 +247,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(f"{w.name}@{w.N}"),
             "avg_launch_ms": avg_ms,
             "launches": n_k,
             "algorithmic_bytes_per_launch": bytes_per_launch,

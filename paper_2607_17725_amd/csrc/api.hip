@@ -413,17 +413,93 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   A[0] = assemble_blocks(h->n0, h->n0, c0, c0, ke);
   progress("hierarchy: level 0 assembled, n=%lld nnz=%lld", static_cast<long long>(A[0].n_rows),
            static_cast<long long>(A[0].rp.back()));
-  HostBlocks kcur = std::move(ke);
+  // element-wise Galerkin products on the device; the coarse blocks stay
+  // resident as the next level's fine blocks
+  auto kmem = std::make_unique<DevMem>();
+  const int64_t *kfoff = kmem->upload(ke.off, s);
+  const double *kf = kmem->upload(ke.val, s);
+  HIPCHECK(hipStreamSynchronize(s));
+  { HostBlocks().val.swap(ke.val); }
   for (int l = 0; l + 1 < L; ++l) {
     const int64_t nf = g->levels[l].n_dof, nc = g->levels[l + 1].n_dof;
     P[l] = csr_of(g->levels[l].P, nf, nc, "prolongation");
-    HostBlocks knext = galerkin_blocks(cells[l], kcur, g->levels[l].parent, cells[l + 1], P[l]);
-    A[l + 1] = assemble_blocks(nc, nc, cells[l + 1], cells[l + 1], knext);
+    const HostCells &F = cells[l], &C = cells[l + 1];
+    const int64_t ncc = C.n_cells;
+    // children of each coarse cell in increasing order; block offsets; staging
+    std::vector<int64_t> chptr(ncc + 1, 0), child(F.n_cells), ooff(ncc + 1, 0), soff(ncc, -1);
+    for (int64_t f = 0; f < F.n_cells; ++f) chptr[g->levels[l].parent[f] + 1]++;
+    for (int64_t c = 0; c < ncc; ++c) chptr[c + 1] += chptr[c];
+    {
+      std::vector<int64_t> fill(chptr.begin(), chptr.end() - 1);
+      for (int64_t f = 0; f < F.n_cells; ++f) child[fill[g->levels[l].parent[f]]++] = f;
+    }
+    for (int64_t c = 0; c < ncc; ++c) {
+      const int64_t m = C.ptr[c + 1] - C.ptr[c];
+      ooff[c + 1] = ooff[c] + m * m;
+    }
+    // cells whose K_f, P_f and T do not fit the LDS buffer stage in global
+    // scratch; launches are cut into batches of at most 2^26 scratch doubles
+    constexpr int64_t SCRATCH_CAP = int64_t(1) << 26;
+    std::vector<std::pair<int64_t, int64_t>> batches;   // [c0, c1)
+    int64_t need_max = 0, b0 = 0, used = 0;
+    for (int64_t c = 0; c < ncc; ++c) {
+      const int64_t m = C.ptr[c + 1] - C.ptr[c];
+      int64_t mf = 0;
+      for (int64_t q = chptr[c]; q < chptr[c + 1]; ++q) mf = std::max(mf, F.ptr[child[q] + 1] - F.ptr[child[q]]);
+      const int64_t need = mf * mf + 2 * mf * m;
+      if (need > GALERKIN_LDS_DOUBLES) {
+        check(need <= SCRATCH_CAP, "coarse cell too large for the Galerkin staging buffer");
+        if (used + need > SCRATCH_CAP) {
+          batches.emplace_back(b0, c);
+          b0 = c;
+          used = 0;
+        }
+        soff[c] = used;
+        used += need;
+        need_max = std::max(need_max, used);
+      }
+    }
+    batches.emplace_back(b0, ncc);
+    DevMem tmp;
+    const int64_t *d_fptr = tmp.upload(F.ptr, s);
+    const int32_t *d_fdof = tmp.upload(F.dof, s);
+    const int64_t *d_prp = tmp.upload(P[l].rp, s);
+    const int32_t *d_pci = tmp.upload(P[l].ci, s);
+    const double *d_pv = tmp.upload(P[l].v, s);
+    const int64_t *d_cptr = tmp.upload(C.ptr, s);
+    const int32_t *d_cdof = tmp.upload(C.dof, s);
+    const int64_t *d_chptr = tmp.upload(chptr, s);
+    const int64_t *d_child = tmp.upload(child, s);
+    const int64_t *d_soff = tmp.upload(soff, s);
+    double *scratch = tmp.alloc<double>(std::max<int64_t>(need_max, 1));
+    int *bad = tmp.alloc<int>(1);
+    const int big = 0x7fffffff;
+    HIPCHECK(hipMemcpyAsync(bad, &big, sizeof(int), hipMemcpyHostToDevice, s));
+    auto knew = std::make_unique<DevMem>();
+    const int64_t *d_ooff = knew->upload(ooff, s);
+    double *d_out = knew->alloc<double>(std::max<int64_t>(ooff[ncc], 1));
+    HIPCHECK(hipMemsetAsync(d_out, 0, sizeof(double) * std::max<int64_t>(ooff[ncc], 1), s));
+    for (const auto &bt : batches)
+      galerkin(bt.first, bt.second - bt.first, d_fptr, d_fdof, kfoff, kf, d_prp, d_pci, d_pv, d_cptr, d_cdof,
+               d_chptr, d_child, d_ooff, d_out, d_soff, scratch, bad, s);
+    int hbad = big;
+    HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HostBlocks knext;
+    knext.off.assign(ooff.begin(), ooff.end() - 1);
+    knext.val.resize(ooff[ncc]);
+    if (ooff[ncc]) HIPCHECK(hipMemcpyAsync(knext.val.data(), d_out, sizeof(double) * ooff[ncc], hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (hbad != big)
+      throw SetupError{FVEM_ERR_INVALID, "prolongation row " + std::to_string(hbad) +
+                                             " references a DOF outside the parent cell (not diffusion-free)"};
+    A[l + 1] = assemble_blocks(nc, nc, C, C, knext);
     progress("hierarchy: Galerkin level %d, n=%lld nnz=%lld", l + 1, static_cast<long long>(nc),
              static_cast<long long>(A[l + 1].rp.back()));
-    kcur = std::move(knext);
+    kmem = std::move(knew);
+    kfoff = d_ooff;
+    kf = d_out;
   }
-  { HostBlocks().val.swap(kcur.val); }
+  kmem.reset();
 
   // level order: rows sorted by length inside windows of 4096 (sliced
   // storage pads each 64-row slice to its longest row); every level

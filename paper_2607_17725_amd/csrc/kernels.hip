@@ -534,6 +534,75 @@ void project_components(int64_t n, double *v, const int32_t *comp, int n_comp, d
   }
 }
 
+// ---------------------------------------------------------------- Galerkin product (setup)
+//
+// One workgroup per coarse cell.  For each child in increasing order: K_f
+// and the dense P_f (rows of the child's DOFs, columns E's local DOFs) are
+// staged in LDS, T = K_f P_f is formed, and every thread adds its own
+// entries of P_f^T T to K_E in global memory, so the result does not depend
+// on scheduling.  Cells whose staging exceeds the LDS buffer use a slice of
+// a global scratch buffer instead.
+
+__global__ __launch_bounds__(256) void galerkin_kernel(int64_t c0, const int64_t *fptr, const int32_t *fdof,
+                                                       const int64_t *kfoff, const double *kf, const int64_t *prp,
+                                                       const int32_t *pci, const double *pv, const int64_t *cptr,
+                                                       const int32_t *cdof, const int64_t *chptr,
+                                                       const int64_t *child, const int64_t *ooff, double *out,
+                                                       const int64_t *soff, double *scratch, int *bad) {
+  extern __shared__ double lds[];
+  const int64_t E = c0 + blockIdx.x;
+  const int t = threadIdx.x;
+  const int m = static_cast<int>(cptr[E + 1] - cptr[E]);
+  const int32_t *cd = cdof + cptr[E];
+  double *base = soff[E] >= 0 ? scratch + soff[E] : lds;
+  double *KE = out + ooff[E];
+  for (int64_t q = chptr[E]; q < chptr[E + 1]; ++q) {
+    const int64_t f = child[q];
+    const int nf = static_cast<int>(fptr[f + 1] - fptr[f]);
+    const int32_t *fd = fdof + fptr[f];
+    double *Kf = base, *Pf = base + nf * nf, *T = Pf + nf * m;
+    const double *kblk = kf + kfoff[f];
+    for (int i = t; i < nf * nf; i += 256) Kf[i] = kblk[i];
+    for (int i = t; i < nf * m; i += 256) Pf[i] = 0.0;
+    __syncthreads();
+    for (int a = t; a < nf; a += 256) {
+      const int32_t row = fd[a];
+      if (row < 0) continue;
+      for (int64_t k = prp[row]; k < prp[row + 1]; ++k) {
+        const int32_t J = pci[k];
+        int b = 0;
+        while (b < m && cd[b] != J) ++b;
+        if (b == m) atomicMin(bad, row);
+        else Pf[a * m + b] = pv[k];
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < nf * m; i += 256) {
+      const int a = i / m, j = i - a * m;
+      double acc = 0.0;
+      for (int b = 0; b < nf; ++b) acc += Kf[a * nf + b] * Pf[b * m + j];
+      T[i] = acc;
+    }
+    __syncthreads();
+    for (int i = t; i < m * m; i += 256) {
+      const int r = i / m, j = i - r * m;
+      double acc = 0.0;
+      for (int a = 0; a < nf; ++a) acc += Pf[a * m + r] * T[a * m + j];
+      KE[i] += acc;
+    }
+    __syncthreads();
+  }
+}
+
+void galerkin(int64_t c0, int64_t ncells, const int64_t *fptr, const int32_t *fdof, const int64_t *kfoff,
+              const double *kf, const int64_t *prp, const int32_t *pci, const double *pv, const int64_t *cptr,
+              const int32_t *cdof, const int64_t *chptr, const int64_t *child, const int64_t *ooff, double *out,
+              const int64_t *soff, double *scratch, int *bad, hipStream_t s) {
+  if (ncells <= 0) return;
+  galerkin_kernel<<<static_cast<unsigned>(ncells), 256, GALERKIN_LDS_DOUBLES * sizeof(double), s>>>(
+      c0, fptr, fdof, kfoff, kf, prp, pci, pv, cptr, cdof, chptr, child, ooff, out, soff, scratch, bad);
+}
+
 // ---------------------------------------------------------------- dense FP64 (coarsest level)
 //
 // Symmetric positive semi-definite factorisation A = L L^T, right-looking in

@@ -73,6 +73,22 @@ void dots(int64_t n, int ndot, const double *a0, const double *b0, const double 
 void project_components(int64_t n, double *v, const int32_t *comp, int n_comp, double *partial, double *mean,
                         hipStream_t s);
 
+// Element-wise Galerkin product on the device (setup, Sec. 4):
+//   K_E = sum over fine cells f with parent E of P_f^T K_f P_f
+// for coarse cells E in [c0, c0 + ncells).  P_f is the dense block of P's
+// rows of f's DOFs on E's local DOFs (built per child in LDS or, where
+// soff[E] >= 0, in the global scratch at that offset).  fptr/fdof and
+// cptr/cdof are the fine and coarse cell DOF lists (-1: eliminated),
+// kfoff/kf the fine blocks (row-major n_f x n_f), chptr/child the children
+// of each coarse cell in increasing order, ooff/out the coarse blocks
+// (row-major m_E x m_E, zero on entry).  A P row that references a DOF
+// outside E sets *bad to the smallest such fine row.
+constexpr int GALERKIN_LDS_DOUBLES = 8192;
+void galerkin(int64_t c0, int64_t ncells, const int64_t *fptr, const int32_t *fdof, const int64_t *kfoff,
+              const double *kf, const int64_t *prp, const int32_t *pci, const double *pv, const int64_t *cptr,
+              const int32_t *cdof, const int64_t *chptr, const int64_t *child, const int64_t *ooff, double *out,
+              const int64_t *soff, double *scratch, int *bad, hipStream_t s);
+
 // dense FP64 (coarsest level), column-major
 void gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t sai, int64_t sak,
               const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc, bool lower_only,

@@ -34,7 +34,8 @@ def log(msg):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sell_cheb_plates128_traffic.json")
-LAYOUT_SOURCES = [os.path.join(ROOT, "paper_2607_17725_amd", "csrc", f) for f in ("kernels.hip", "setup_host.cpp")]
+LAYOUT_SOURCES = [os.path.join(ROOT, "paper_2607_17725_amd", "csrc", f)
+                  for f in ("sell.hip", "epilogues.hpp", "setup_host.cpp")]
 
 
 def layout_hash():

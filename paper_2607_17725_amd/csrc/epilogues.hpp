@@ -1,0 +1,54 @@
+// Row epilogues of the SpMV kernels: what a kernel does with (A x)_i once a
+// row's sum is complete (store, residual, prolong-and-correct, scaled store,
+// fused Chebyshev step).  Shared by the CSR (kernels.hip) and sliced
+// (sell.hip) SpMV kernels.
+#pragma once
+
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace fvem {
+
+template <typename T>
+struct EpiStore {
+  using acc_t = T;
+  T *y;
+  __device__ void operator()(int64_t i, T a) const { y[i] = a; }
+};
+
+template <typename T>
+struct EpiResidual {  // y = b - A x
+  using acc_t = T;
+  const T *b;
+  T *y;
+  __device__ void operator()(int64_t i, T a) const { y[i] = b[i] - a; }
+};
+
+template <typename T>
+struct EpiAdd {  // y += A x  (prolong-and-correct)
+  using acc_t = T;
+  T *y;
+  __device__ void operator()(int64_t i, T a) const { y[i] += a; }
+};
+
+struct EpiScaled {  // y = alpha A x
+  using acc_t = double;
+  double *y;
+  double alpha;
+  __device__ void operator()(int64_t i, double a) const { y[i] = alpha * a; }
+};
+
+template <typename T>
+struct EpiCheb {  // d = ca d + cb dinv (b - A xin);  xout = xin + d
+  using acc_t = T;
+  const T *b, *dinv, *xin;
+  T *d, *xout;
+  T ca, cb;
+  __device__ void operator()(int64_t i, T a) const {
+    const T dn = ca * d[i] + cb * dinv[i] * (b[i] - a);
+    d[i] = dn;
+    xout[i] = xin[i] + dn;
+  }
+};
+
+}  // namespace fvem

@@ -4,6 +4,7 @@
 // the only dense contraction is the coarsest-level factorisation, which runs
 // on FP64 MFMA.
 #include "kernels.hpp"
+#include "epilogues.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -39,48 +40,6 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n, const int64_t *__r
   if (lane == 0) epi(row, acc);
 }
 
-template <typename T>
-struct EpiStore {
-  using acc_t = T;
-  T *y;
-  __device__ void operator()(int64_t i, T a) const { y[i] = a; }
-};
-
-template <typename T>
-struct EpiResidual {  // y = b - A x
-  using acc_t = T;
-  const T *b;
-  T *y;
-  __device__ void operator()(int64_t i, T a) const { y[i] = b[i] - a; }
-};
-
-template <typename T>
-struct EpiAdd {  // y += A x  (prolong-and-correct)
-  using acc_t = T;
-  T *y;
-  __device__ void operator()(int64_t i, T a) const { y[i] += a; }
-};
-
-struct EpiScaled {  // y = alpha A x
-  using acc_t = double;
-  double *y;
-  double alpha;
-  __device__ void operator()(int64_t i, double a) const { y[i] = alpha * a; }
-};
-
-template <typename T>
-struct EpiCheb {  // d = ca d + cb dinv (b - A xin);  xout = xin + d
-  using acc_t = T;
-  const T *b, *dinv, *xin;
-  T *d, *xout;
-  T ca, cb;
-  __device__ void operator()(int64_t i, T a) const {
-    const T dn = ca * d[i] + cb * dinv[i] * (b[i] - a);
-    d[i] = dn;
-    xout[i] = xin[i] + dn;
-  }
-};
-
 static int group_for(int64_t n, int64_t nnz) {
   const double avg = n > 0 ? static_cast<double>(nnz) / n : 1.0;
   if (avg > 96) return 64;
@@ -102,154 +61,6 @@ static void launch_spmv(const DevCSRView<VT> &A, const XT *x, Epi epi, hipStream
     default: spmv_kernel<8, VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, A.v, x, epi); break;
   }
 }
-
-// Sliced ELLPACK: one wavefront per 64-row slice, one lane per row, so the
-// value and column loads of a step are contiguous reads per wavefront.  Rows
-// inside each window of the level
-// order are sorted by length at setup, so a slice's rows have (nearly) equal
-// length and padding is a few percent.  The matrix is streamed once per
-// launch with non-temporal loads, leaving the caches to the gathered x.
-// Workgroups are dispatched round-robin over the 8 XCDs; remapping the
-// workgroup id gives each XCD a contiguous range of slices, so x entries
-// shared by neighbouring slices are reused in that XCD's L2.
-
-__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t nb) {
-  const int64_t q = nb >> 3, r = nb & 7;
-  const int64_t xcd = b & 7, idx = b >> 3;
-  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
-
-// 4-wide vectors for the interleaved groups of 4 entries
-typedef int32_t int4v __attribute__((ext_vector_type(4)));
-typedef float float4v __attribute__((ext_vector_type(4)));
-typedef double double2v __attribute__((ext_vector_type(2)));
-
-template <typename T> struct Quad;
-template <> struct Quad<float> {
-  __device__ static void load_nt(const float *p, float v[4]) {
-    const float4v q = __builtin_nontemporal_load(reinterpret_cast<const float4v *>(p));
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-  }
-  __device__ static void load(const float *p, float v[4]) {
-    const float4v q = *reinterpret_cast<const float4v *>(p);
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-  }
-};
-template <> struct Quad<double> {
-  __device__ static void load_nt(const double *p, double v[4]) {
-    const double2v a = __builtin_nontemporal_load(reinterpret_cast<const double2v *>(p));
-    const double2v b = __builtin_nontemporal_load(reinterpret_cast<const double2v *>(p + 2));
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-  }
-  __device__ static void load(const double *p, double v[4]) {
-    const double2v a = *reinterpret_cast<const double2v *>(p);
-    const double2v b = *reinterpret_cast<const double2v *>(p + 2);
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-  }
-};
-
-// Entry j of lane r of a slice sits at 256 (j / 4) + 4 r + j % 4 from the
-// slice start: each group of 4 entries is one 16-byte load per lane and one
-// contiguous 1 KiB read per wavefront.  Two groups are in flight per step.
-// 8 slices (wavefronts) per workgroup: with the level order's spatially
-// ordered slices this is one 4x4x4-cell tile of k = 2 DOFs, whose gathers
-// of x share the CU's L1.
-constexpr int SELL_WAVES = 8;
-
-template <typename VT, typename XT, class Epi>
-__global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_t nslices, const int64_t *__restrict__ sp,
-                                                   const int32_t *__restrict__ sl, const int32_t *__restrict__ ci,
-                                                   const int64_t *__restrict__ vp, const VT *__restrict__ val,
-                                                   const int32_t *__restrict__ tid, const VT *__restrict__ tv,
-                                                   int32_t tw, const XT *__restrict__ x, Epi epi) {
-  const int64_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int64_t slice = blk * SELL_WAVES + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (slice >= nslices) return;
-  using AT = typename Epi::acc_t;
-  const int groups = sl[slice] >> 2;
-  const int32_t *cp = ci + sp[slice] + 4 * lane;
-  const int64_t vb = vp[slice];
-  AT acc = 0;
-  auto fma4 = [&](const int4v c, const VT v[4]) {
-    acc += static_cast<AT>(v[0]) * static_cast<AT>(x[c.x]);
-    acc += static_cast<AT>(v[1]) * static_cast<AT>(x[c.y]);
-    acc += static_cast<AT>(v[2]) * static_cast<AT>(x[c.z]);
-    acc += static_cast<AT>(v[3]) * static_cast<AT>(x[c.w]);
-  };
-  auto cols = [&](int g) { return __builtin_nontemporal_load(reinterpret_cast<const int4v *>(cp + 256 * static_cast<int64_t>(g))); };
-  if (vb >= 0) {
-    // values stored with the slice, in the same interleaved layout
-    const VT *vq = val + vb + 4 * lane;
-    int g = 0;
-    for (; g + 2 <= groups; g += 2) {
-      const int4v c0 = cols(g), c1 = cols(g + 1);
-      VT v0[4], v1[4];
-      Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g), v0);
-      Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g + 1), v1);
-      fma4(c0, v0);
-      fma4(c1, v1);
-    }
-    if (g < groups) {
-      const int4v c0 = cols(g);
-      VT v0[4];
-      Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g), v0);
-      fma4(c0, v0);
-    }
-  } else {
-    // every row of the slice repeats a template row: values come from the
-    // small template table (cache resident), only the columns stream
-    const VT *tq = tv + static_cast<int64_t>(tid[slice * 64 + lane]) * tw;
-    int g = 0;
-    for (; g + 2 <= groups; g += 2) {
-      const int4v c0 = cols(g), c1 = cols(g + 1);
-      VT v0[4], v1[4];
-      Quad<VT>::load(tq + 4 * g, v0);
-      Quad<VT>::load(tq + 4 * g + 4, v1);
-      fma4(c0, v0);
-      fma4(c1, v1);
-    }
-    if (g < groups) {
-      const int4v c0 = cols(g);
-      VT v0[4];
-      Quad<VT>::load(tq + 4 * g, v0);
-      fma4(c0, v0);
-    }
-  }
-  const int64_t row = slice * 64 + lane;
-  if (row < n) epi(row, acc);
-}
-
-template <typename VT, typename XT, class Epi>
-static void launch_sell(const DevSELLView<VT> &A, const XT *x, Epi epi, hipStream_t s) {
-  if (A.nslices == 0) return;
-  const dim3 grid(static_cast<unsigned>((A.nslices + SELL_WAVES - 1) / SELL_WAVES));
-  sell_kernel<VT, XT, Epi><<<grid, 64 * SELL_WAVES, 0, s>>>(A.n, A.nslices, A.sp, A.sl, A.ci, A.vp, A.v, A.tid, A.tv, A.tw, x,
-                                                epi);
-}
-
-template <typename T>
-void spmv(const DevSELLView<T> &A, const T *x, T *y, hipStream_t s) {
-  launch_sell(A, x, EpiStore<T>{y}, s);
-}
-template <typename T>
-void residual(const DevSELLView<T> &A, const T *x, const T *b, T *r, hipStream_t s) {
-  launch_sell(A, x, EpiResidual<T>{b, r}, s);
-}
-template <typename T>
-void cheb_step(const DevSELLView<T> &A, const T *b, const T *dinv, const T *xin, T *d, T *xout, T ca, T cb,
-               hipStream_t s) {
-  launch_sell(A, xin, EpiCheb<T>{b, dinv, xin, d, xout, ca, cb}, s);
-}
-template void spmv<double>(const DevSELLView<double> &, const double *, double *, hipStream_t);
-template void spmv<float>(const DevSELLView<float> &, const float *, float *, hipStream_t);
-template void residual<double>(const DevSELLView<double> &, const double *, const double *, double *,
-                               hipStream_t);
-template void residual<float>(const DevSELLView<float> &, const float *, const float *, float *, hipStream_t);
-template void cheb_step<double>(const DevSELLView<double> &, const double *, const double *, const double *,
-                                double *, double *, double, double, hipStream_t);
-template void cheb_step<float>(const DevSELLView<float> &, const float *, const float *, const float *, float *,
-                               float *, float, float, hipStream_t);
 
 template <typename T>
 void spmv(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s) {

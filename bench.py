@@ -239,6 +239,8 @@ def main():
                          f"tol {w.tol}, {args.precision} precision"),
             "N": w.N, "k": w.k, "levels": hier.n_levels, "n_dof": n0, "nnz_K": nnz0,
             "rhs_per_step": len(U), "iterations": [min(its), max(its)],
+            "level_nnz": [hier.level_storage(l)["nnz"] for l in range(hier.n_levels)],
+            "level_templated_rows": [hier.level_storage(l)["rows_templated"] for l in range(hier.n_levels)],
             "max_rel_residual": max(res), "setup_s": t_grid + t_hier,
         },
         "roofline": {

@@ -93,8 +93,9 @@ struct DevSELL {
   std::vector<int64_t> hsp;
   std::vector<int32_t> hsl, hrl;
   HostValues hv64;                  // FP64 value set without its values (read back on demand)
-  DevSELLView<double> d() const { return {n, m, nslices, sp, sl, ci, d64.vp, v64, d64.tid, tv64, d64.tw}; }
-  DevSELLView<float> f() const { return {n, m, nslices, sp, sl, ci, d32.vp, v32, d32.tid, tv32, d32.tw}; }
+  bool split = false;
+  DevSELLView<double> d() const { return {n, m, nslices, sp, sl, ci, d64.vp, v64, d64.tid, tv64, d64.tw, split}; }
+  DevSELLView<float> f() const { return {n, m, nslices, sp, sl, ci, d32.vp, v32, d32.tid, tv32, d32.tw, split}; }
 };
 
 struct Level {
@@ -348,6 +349,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const int64_t dense_max = (o && o->coarse_dense_max > 0) ? o->coarse_dense_max : 16384;
   const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 0.0;
   const double shift = (o && o->coarse_shift > 0) ? o->coarse_shift : 1e-8;
+  const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 131072;
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
   h->lv.resize(L);
@@ -526,6 +528,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     Level &V = h->lv[l];
     V.n = A[l].n_rows;
     V.A = upload_sell(h, A[l], true, s);
+    V.A.split = small_rows >= 0 && V.n <= small_rows;
     std::vector<double> dinv(V.n);
     for (int64_t i = 0; i < V.n; ++i) {
       double d = 0.0;

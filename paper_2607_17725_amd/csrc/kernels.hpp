@@ -34,6 +34,7 @@ struct DevSELLView {
   const int32_t *tid = nullptr;
   const T *tv = nullptr;
   int32_t tw = 0;
+  bool split = false;   // several lanes per row (small levels)
 };
 
 // SpMV family on the sliced layout (level operators; fused epilogues)

@@ -124,12 +124,59 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_
   if (row < n) epi(row, acc);
 }
 
+// Small levels (a few thousand slices) cannot fill 256 CUs with one
+// wavefront per slice, and each wavefront would walk its rows' 60-300
+// entries serially.  There, SPLIT lanes share a row: lane k of a row takes
+// the row's groups k, k + SPLIT, ... in order, and the lanes' sums are
+// combined by a fixed butterfly, so the result is still deterministic.
+constexpr int SELL_SPLIT = 16;
+
+template <typename VT, typename XT, class Epi>
+__global__ __launch_bounds__(256) void sell_split_kernel(int64_t n, const int64_t *__restrict__ sp,
+                                                         const int32_t *__restrict__ sl,
+                                                         const int32_t *__restrict__ ci,
+                                                         const int64_t *__restrict__ vp, const VT *__restrict__ val,
+                                                         const int32_t *__restrict__ tid,
+                                                         const VT *__restrict__ tv, int32_t tw,
+                                                         const XT *__restrict__ x, Epi epi) {
+  const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / SELL_SPLIT;
+  const int k = threadIdx.x % SELL_SPLIT;
+  if (row >= n) return;
+  using AT = typename Epi::acc_t;
+  const int64_t slice = row >> 6;
+  const int q = static_cast<int>(row & 63);
+  const int groups = sl[slice] >> 2;
+  const int32_t *cp = ci + sp[slice] + 4 * q;
+  const int64_t vb = vp[slice];
+  const VT *vq = vb >= 0 ? val + vb + 4 * q : nullptr;
+  const VT *tq = vb >= 0 ? nullptr : tv + static_cast<int64_t>(tid[row]) * tw;
+  AT acc = 0;
+  for (int g = k; g < groups; g += SELL_SPLIT) {
+    const int4v c = *reinterpret_cast<const int4v *>(cp + 256 * static_cast<int64_t>(g));
+    VT v[4];
+    if (vq) Quad<VT>::load(vq + 256 * static_cast<int64_t>(g), v);
+    else Quad<VT>::load(tq + 4 * g, v);
+    acc += static_cast<AT>(v[0]) * static_cast<AT>(x[c.x]);
+    acc += static_cast<AT>(v[1]) * static_cast<AT>(x[c.y]);
+    acc += static_cast<AT>(v[2]) * static_cast<AT>(x[c.z]);
+    acc += static_cast<AT>(v[3]) * static_cast<AT>(x[c.w]);
+  }
+#pragma unroll
+  for (int o = SELL_SPLIT / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SELL_SPLIT);
+  if (k == 0) epi(row, acc);
+}
+
 template <typename VT, typename XT, class Epi>
 static void launch_sell(const DevSELLView<VT> &A, const XT *x, Epi epi, hipStream_t s) {
   if (A.nslices == 0) return;
+  if (A.split) {
+    const dim3 grid(static_cast<unsigned>((A.n * SELL_SPLIT + 255) / 256));
+    sell_split_kernel<VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.sp, A.sl, A.ci, A.vp, A.v, A.tid, A.tv, A.tw, x, epi);
+    return;
+  }
   const dim3 grid(static_cast<unsigned>((A.nslices + SELL_WAVES - 1) / SELL_WAVES));
-  sell_kernel<VT, XT, Epi><<<grid, 64 * SELL_WAVES, 0, s>>>(A.n, A.nslices, A.sp, A.sl, A.ci, A.vp, A.v, A.tid, A.tv, A.tw, x,
-                                                epi);
+  sell_kernel<VT, XT, Epi><<<grid, 64 * SELL_WAVES, 0, s>>>(A.n, A.nslices, A.sp, A.sl, A.ci, A.vp, A.v, A.tid,
+                                                            A.tv, A.tw, x, epi);
 }
 
 template <typename T>

@@ -54,7 +54,7 @@ class _Grid(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("cheb_degree", ctypes.c_int32), ("cheb_lower", ctypes.c_double),
                 ("coarse_dense_max", ctypes.c_int32), ("coarse_rcond", ctypes.c_double),
-                ("coarse_shift", ctypes.c_double)]
+                ("coarse_shift", ctypes.c_double), ("small_level_rows", ctypes.c_int64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -157,7 +157,7 @@ class Hierarchy:
     """
 
     def __init__(self, desc, stream=None, cheb_degree=5, cheb_lower=1.0 / 30.0, coarse_dense_max=16384,
-                 coarse_rcond=0.0, coarse_shift=1e-8):
+                 coarse_rcond=0.0, coarse_shift=1e-8, small_level_rows=0):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -166,7 +166,7 @@ class Hierarchy:
             g = _Grid()
             _check(lib.fvem_grid_describe(desc._g, ctypes.byref(g)))
             self._finish(lib, g, [desc], stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond,
-                         coarse_shift)
+                         coarse_shift, small_level_rows)
             return
         keep = []
         L = len(desc["levels"])
@@ -206,11 +206,13 @@ class Hierarchy:
         g.vc_len = len(desc["vc_val"]) if desc.get("vc_val") is not None else 0
         g.n_vert = int(desc.get("n_vert", 0))
         g.n_components = int(desc.get("n_components", 0))
-        self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift)
+        self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
+                     small_level_rows)
 
-    def _finish(self, lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift):
+    def _finish(self, lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
+                small_level_rows):
         import torch
-        opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift)
+        opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift, small_level_rows)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         _check(lib.fvem_hierarchy_build(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),

@@ -189,3 +189,26 @@ def test_error_paths(request):
     with pytest.raises(fvem.FvemError) as e:
         fvem.Hierarchy(d)
     assert e.value.code == 1
+
+
+@pytest.mark.parametrize("name", ["c3_small", "c4_small"])
+def test_whole_slice_kernel_on_every_level(name, request):
+    """The oracle-sized levels normally use the row-split kernel (16 lanes per
+    row); forcing the whole-slice kernel (one lane per row, the one the large
+    levels run) on every level must give the same answers."""
+    import synth
+    from paper_2607_17725_amd import fvem
+    pb = request.getfixturevalue(name)
+    h = _hier(pb, small_level_rows=-1)
+    rng = np.random.default_rng(5)
+    r = pb.null.project(rng.standard_normal(pb.K.shape[0]))
+    z_ref = pb.null.project(pb.mg.vcycle(r))
+    z = pb.null.project(_host(h.apply(fvem.OP_VCYCLE, _dev(r))))
+    tol = 1e-6 if name == "c4_small" else 1e-8   # see test_vcycle_fp64_matches_oracle
+    assert np.linalg.norm(z - z_ref) <= tol * np.linalg.norm(z_ref)
+    z32 = pb.null.project(_host(h.apply(fvem.OP_VCYCLE32, _dev(r))))
+    assert np.linalg.norm(z32 - z_ref) <= 1e-4 * np.linalg.norm(z_ref)
+    u = synth.normal_field(pb.vertices, 0).ravel()
+    p, st = h.solve(_dev(u), tol=1e-10, precision=1, maxit=1000)
+    p_ref = pb.solve_direct(u)
+    assert np.linalg.norm(_host(p) - p_ref) <= 1e-6 * np.linalg.norm(p_ref)

@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-N", type=int, default=16)
     ap.add_argument("--rhs", type=int, default=16, help="right-hand sides per step (profiling runs use fewer)")
+    ap.add_argument("--small-level-rows", type=int, default=0,
+                    help="levels up to this many rows use the row-split SpMV (0: library default, <0: never)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB buffer 3 times (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -142,7 +144,7 @@ def main():
     log(f"grid built in {t_grid:.1f} s: {grid.n_dof} DOFs, {grid.n_vert} vertices, {grid.n_trees} cut cells")
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    hier = fvem.Hierarchy(grid, stream=stream)
+    hier = fvem.Hierarchy(grid, stream=stream, small_level_rows=args.small_level_rows)
     torch.cuda.synchronize()
     t_hier = time.perf_counter() - t0
     n0 = hier.n_dof

@@ -349,7 +349,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const int64_t dense_max = (o && o->coarse_dense_max > 0) ? o->coarse_dense_max : 16384;
   const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 0.0;
   const double shift = (o && o->coarse_shift > 0) ? o->coarse_shift : 1e-8;
-  const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 131072;
+  const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 1048576;
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
   h->lv.resize(L);

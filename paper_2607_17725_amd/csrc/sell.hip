@@ -54,7 +54,9 @@ template <> struct Quad<double> {
 
 // Entry j of lane r of a slice sits at 256 (j / 4) + 4 r + j % 4 from the
 // slice start: each group of 4 entries is one 16-byte load per lane and one
-// contiguous 1 KiB read per wavefront.  Two groups are in flight per step.
+// contiguous 1 KiB read per wavefront.  SELL_GROUPS groups are in flight per
+// step.
+constexpr int SELL_GROUPS = 4;
 // 8 slices (wavefronts) per workgroup: with the level order's spatially
 // ordered slices this is one 4x4x4-cell tile of k = 2 DOFs, whose gathers
 // of x share the CU's L1.
@@ -86,15 +88,18 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_
     // values stored with the slice, in the same interleaved layout
     const VT *vq = val + vb + 4 * lane;
     int g = 0;
-    for (; g + 2 <= groups; g += 2) {
-      const int4v c0 = cols(g), c1 = cols(g + 1);
-      VT v0[4], v1[4];
-      Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g), v0);
-      Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g + 1), v1);
-      fma4(c0, v0);
-      fma4(c1, v1);
+    for (; g + SELL_GROUPS <= groups; g += SELL_GROUPS) {
+      int4v c[SELL_GROUPS];
+      VT v[SELL_GROUPS][4];
+#pragma unroll
+      for (int u = 0; u < SELL_GROUPS; ++u) {
+        c[u] = cols(g + u);
+        Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g + u), v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < SELL_GROUPS; ++u) fma4(c[u], v[u]);
     }
-    if (g < groups) {
+    for (; g < groups; ++g) {
       const int4v c0 = cols(g);
       VT v0[4];
       Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g), v0);
@@ -105,15 +110,18 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_
     // small template table (cache resident), only the columns stream
     const VT *tq = tv + static_cast<int64_t>(tid[slice * 64 + lane]) * tw;
     int g = 0;
-    for (; g + 2 <= groups; g += 2) {
-      const int4v c0 = cols(g), c1 = cols(g + 1);
-      VT v0[4], v1[4];
-      Quad<VT>::load(tq + 4 * g, v0);
-      Quad<VT>::load(tq + 4 * g + 4, v1);
-      fma4(c0, v0);
-      fma4(c1, v1);
+    for (; g + SELL_GROUPS <= groups; g += SELL_GROUPS) {
+      int4v c[SELL_GROUPS];
+      VT v[SELL_GROUPS][4];
+#pragma unroll
+      for (int u = 0; u < SELL_GROUPS; ++u) {
+        c[u] = cols(g + u);
+        Quad<VT>::load(tq + 4 * (g + u), v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < SELL_GROUPS; ++u) fma4(c[u], v[u]);
     }
-    if (g < groups) {
+    for (; g < groups; ++g) {
       const int4v c0 = cols(g);
       VT v0[4];
       Quad<VT>::load(tq + 4 * g, v0);

@@ -94,14 +94,19 @@ struct DevSELL {
   std::vector<int32_t> hsl, hrl;
   HostValues hv64;                  // FP64 value set without its values (read back on demand)
   bool split = false;
-  DevSELLView<double> d() const { return {n, m, nslices, sp, sl, ci, d64.vp, v64, d64.tid, tv64, d64.tw, split}; }
-  DevSELLView<float> f() const { return {n, m, nslices, sp, sl, ci, d32.vp, v32, d32.tid, tv32, d32.tw, split}; }
+  int32_t *rowmap = nullptr;        // transfers: stored row r is output row rowmap[r]
+  DevSELLView<double> d() const {
+    return {n, m, nslices, sp, sl, ci, d64.vp, v64, d64.tid, tv64, d64.tw, split, rowmap};
+  }
+  DevSELLView<float> f() const {
+    return {n, m, nslices, sp, sl, ci, d32.vp, v32, d32.tid, tv32, d32.tw, split, rowmap};
+  }
 };
 
 struct Level {
   int64_t n = 0;
   DevSELL A;
-  DevCSR P, R;
+  DevSELL P, R;   // transfers in their own length-sorted row order (rowmap)
   std::vector<int32_t> order;   // level order: order[internal] = caller's DOF index
   double *dinv64 = nullptr;
   float *dinv32 = nullptr;
@@ -542,8 +547,18 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     V.lmax = gershgorin_scaled(A[l]);
     cheb_coefficients(V, deg, lower);
     if (l + 1 < L) {
-      V.P = upload_csr(h, P[l], true, s);
-      V.R = upload_csr(h, transpose(P[l]), true, s);
+      // transfers: rows sorted by length inside windows (own order), values
+      // from templates where rows repeat; outputs are scattered back by rowmap
+      auto transfer = [&](const HostCSR &T) {
+        const std::vector<int32_t> ord = window_order(T, ORDER_WINDOW);
+        DevSELL d = upload_sell(h, permute(T, ord, nullptr), true, s);
+        d.rowmap = h->mem.upload(ord, s);
+        d.split = small_rows >= 0 && d.n <= small_rows;
+        HIPCHECK(hipStreamSynchronize(s));
+        return d;
+      };
+      V.P = transfer(P[l]);
+      V.R = transfer(transpose(P[l]));
     }
     V.b64 = h->mem.alloc<double>(V.n);
     V.x64 = h->mem.alloc<double>(V.n);
@@ -637,8 +652,8 @@ template <> struct Vec<double> {
   static double *r(Level &L) { return L.r64; }
   static const double *dinv(Level &L) { return L.dinv64; }
   static DevSELLView<double> A(Level &L) { return L.A.d(); }
-  static DevCSRView<double> P(Level &L) { return L.P.d(); }
-  static DevCSRView<double> R(Level &L) { return L.R.d(); }
+  static DevSELLView<double> P(Level &L) { return L.P.d(); }
+  static DevSELLView<double> R(Level &L) { return L.R.d(); }
 };
 template <> struct Vec<float> {
   static float *b(Level &L) { return L.b32; }
@@ -648,8 +663,8 @@ template <> struct Vec<float> {
   static float *r(Level &L) { return L.r32; }
   static const float *dinv(Level &L) { return L.dinv32; }
   static DevSELLView<float> A(Level &L) { return L.A.f(); }
-  static DevCSRView<float> P(Level &L) { return L.P.f(); }
-  static DevCSRView<float> R(Level &L) { return L.R.f(); }
+  static DevSELLView<float> P(Level &L) { return L.P.f(); }
+  static DevSELLView<float> R(Level &L) { return L.R.f(); }
 };
 
 static void ev_record(fvem_hierarchy *h, hipStream_t s) {

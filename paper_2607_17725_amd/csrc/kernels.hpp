@@ -35,6 +35,7 @@ struct DevSELLView {
   const T *tv = nullptr;
   int32_t tw = 0;
   bool split = false;   // several lanes per row (small levels)
+  const int32_t *rowmap = nullptr;   // stored row r is output row rowmap[r] (null: r)
 };
 
 // SpMV family on the sliced layout (level operators; fused epilogues)
@@ -43,6 +44,7 @@ template <typename T> void residual(const DevSELLView<T> &A, const T *x, const T
 template <typename T>
 void cheb_step(const DevSELLView<T> &A, const T *b, const T *dinv, const T *xin, T *d, T *xout, T ca, T cb,
                hipStream_t s);
+template <typename T> void spmv_add(const DevSELLView<T> &A, const T *x, T *y, hipStream_t s);
 
 // SpMV family (vector CSR with fused epilogues; transfers and divergence)
 template <typename T> void spmv(const DevCSRView<T> &A, const T *x, T *y, hipStream_t s);

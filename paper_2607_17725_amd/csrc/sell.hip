@@ -67,7 +67,8 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_
                                                    const int32_t *__restrict__ sl, const int32_t *__restrict__ ci,
                                                    const int64_t *__restrict__ vp, const VT *__restrict__ val,
                                                    const int32_t *__restrict__ tid, const VT *__restrict__ tv,
-                                                   int32_t tw, const XT *__restrict__ x, Epi epi) {
+                                                   int32_t tw, const int32_t *__restrict__ rowmap,
+                                                   const XT *__restrict__ x, Epi epi) {
   const int64_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
   const int64_t slice = blk * SELL_WAVES + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_
     }
   }
   const int64_t row = slice * 64 + lane;
-  if (row < n) epi(row, acc);
+  if (row < n) epi(rowmap ? static_cast<int64_t>(rowmap[row]) : row, acc);
 }
 
 // Small levels (a few thousand slices) cannot fill 256 CUs with one
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(256) void sell_split_kernel(int64_t n, const int64_
                                                          const int64_t *__restrict__ vp, const VT *__restrict__ val,
                                                          const int32_t *__restrict__ tid,
                                                          const VT *__restrict__ tv, int32_t tw,
+                                                         const int32_t *__restrict__ rowmap,
                                                          const XT *__restrict__ x, Epi epi) {
   const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / SELL_SPLIT;
   const int k = threadIdx.x % SELL_SPLIT;
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(256) void sell_split_kernel(int64_t n, const int64_
   }
 #pragma unroll
   for (int o = SELL_SPLIT / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SELL_SPLIT);
-  if (k == 0) epi(row, acc);
+  if (k == 0) epi(rowmap ? static_cast<int64_t>(rowmap[row]) : row, acc);
 }
 
 template <typename VT, typename XT, class Epi>
@@ -179,12 +181,13 @@ static void launch_sell(const DevSELLView<VT> &A, const XT *x, Epi epi, hipStrea
   if (A.nslices == 0) return;
   if (A.split) {
     const dim3 grid(static_cast<unsigned>((A.n * SELL_SPLIT + 255) / 256));
-    sell_split_kernel<VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.sp, A.sl, A.ci, A.vp, A.v, A.tid, A.tv, A.tw, x, epi);
+    sell_split_kernel<VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.sp, A.sl, A.ci, A.vp, A.v, A.tid, A.tv, A.tw,
+                                                        A.rowmap, x, epi);
     return;
   }
   const dim3 grid(static_cast<unsigned>((A.nslices + SELL_WAVES - 1) / SELL_WAVES));
   sell_kernel<VT, XT, Epi><<<grid, 64 * SELL_WAVES, 0, s>>>(A.n, A.nslices, A.sp, A.sl, A.ci, A.vp, A.v, A.tid,
-                                                            A.tv, A.tw, x, epi);
+                                                            A.tv, A.tw, A.rowmap, x, epi);
 }
 
 template <typename T>
@@ -200,6 +203,12 @@ void cheb_step(const DevSELLView<T> &A, const T *b, const T *dinv, const T *xin,
                hipStream_t s) {
   launch_sell(A, xin, EpiCheb<T>{b, dinv, xin, d, xout, ca, cb}, s);
 }
+template <typename T>
+void spmv_add(const DevSELLView<T> &A, const T *x, T *y, hipStream_t s) {
+  launch_sell(A, x, EpiAdd<T>{y}, s);
+}
+template void spmv_add<double>(const DevSELLView<double> &, const double *, double *, hipStream_t);
+template void spmv_add<float>(const DevSELLView<float> &, const float *, float *, hipStream_t);
 template void spmv<double>(const DevSELLView<double> &, const double *, double *, hipStream_t);
 template void spmv<float>(const DevSELLView<float> &, const float *, float *, hipStream_t);
 template void residual<double>(const DevSELLView<double> &, const double *, const double *, double *,

@@ -193,12 +193,14 @@ def main():
     n_k = sum(s["n_fine_smoother"] for s in stats)
     avg_ms = ms_k / max(n_k, 1)
     # algorithmic bytes of one finest Chebyshev step: the stored operator once
-    # (an int32 column per nonzero; an FP32 value per nonzero of rows that
-    # store values; an int32 template id per row that reads a shared value
-    # template) and six FP32 vector streams (x, b, D^-1, d read; d, x_out
-    # written); slice padding, the cache-resident template table and cache
-    # misses are not counted
-    bytes_per_launch = 4 * nnz0 + 4 * stor["nnz_explicit"] + 4 * stor["rows_templated"] + 24 * n0
+    # (a 16-bit column code per nonzero of coded slices plus their block
+    # tables, an int32 column per nonzero elsewhere; an FP32 value per
+    # nonzero of rows that store values; an int32 template id per row that
+    # reads a shared value template) and six FP32 vector streams (x, b, D^-1,
+    # d read; d, x_out written); slice padding, the cache-resident template
+    # table and cache misses are not counted
+    matrix_bytes = hier.level_bytes(0, fvem.PREC_MIXED)
+    bytes_per_launch = matrix_bytes + 24 * n0
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     log(f"{solves} solves in {dt:.2f} s: {value:.3f} solves/s, iterations {min(its)}-{max(its)}, "
         f"max residual {max(res):.2e}; fine Chebyshev step {avg_ms:.3f} ms avg over {n_k} launches "
@@ -247,7 +249,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "finest-level fused Chebyshev step (FP32 sliced-ELLPACK SpMV with value templates + update)",
+            "kernel": "finest-level fused Chebyshev step (FP32 sliced-ELLPACK SpMV, 16-bit column codes, value templates + update)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -246,11 +246,17 @@ fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n
 /* Storage of level l's operator: nonzeros, nonzeros whose values are stored
  * with their slice, rows whose values come from the shared value templates
  * (their slices store columns only), number of templates and their width.
- * One application of A_l in FP32 reads 4 nnz + 4 nnz_explicit +
- * 4 rows_templated bytes of matrix data (plus 4 n_templates template_width,
- * cache resident). */
+ * (FP32 value set; fvem_level_bytes gives the bytes one application reads). */
 fvem_status fvem_level_storage(fvem_hierarchy *h, int32_t level, int64_t *nnz, int64_t *nnz_explicit,
                                int64_t *rows_templated, int32_t *n_templates, int32_t *template_width);
+
+/* Matrix bytes one application of A_l reads in the given precision
+ * (fvem_precision: FP64 or MIXED = FP32 values): 2 bytes per nonzero of
+ * slices with 16-bit column codes plus 256 per block table, 4 per nonzero
+ * of the others, the stored values (4 or 8 bytes per nonzero of
+ * value-storing rows) and 4 per row reading a value template.  Padding and
+ * the cache-resident template table are not counted. */
+fvem_status fvem_level_bytes(fvem_hierarchy *h, int32_t level, int32_t precision, int64_t *bytes);
 
 /* Number of level-0 cells carrying velocity fields (0 without vc_off). */
 fvem_status fvem_hierarchy_cells(fvem_hierarchy *h, int64_t *n_cells);

@@ -83,23 +83,26 @@ struct DevValues {
 };
 
 struct DevSELL {
-  int64_t n = 0, m = 0, nnz = 0, nslices = 0, stored = 0;
-  int64_t *sp = nullptr;
+  int64_t n = 0, m = 0, nnz = 0, nslices = 0;
+  int64_t *cp = nullptr, *bt = nullptr;
   int32_t *sl = nullptr;
-  int32_t *ci = nullptr;
+  int32_t *ci = nullptr, *btab = nullptr;
+  uint16_t *c16 = nullptr;
+  int64_t n_ci = 0, n_c16 = 0;
+  int64_t col_bytes = 0;            // algorithmic column bytes: 2 or 4 per nonzero, 256 per block table
   DevValues d64, d32;               // exact FP64 and single-precision value sets
   double *v64 = nullptr, *tv64 = nullptr;
   float *v32 = nullptr, *tv32 = nullptr;
-  std::vector<int64_t> hsp;
-  std::vector<int32_t> hsl, hrl;
+  std::vector<int64_t> hsp, hcp, hbt;
+  std::vector<int32_t> hsl, hrl, hbtab;
   HostValues hv64;                  // FP64 value set without its values (read back on demand)
   bool split = false;
   int32_t *rowmap = nullptr;        // transfers: stored row r is output row rowmap[r]
   DevSELLView<double> d() const {
-    return {n, m, nslices, sp, sl, ci, d64.vp, v64, d64.tid, tv64, d64.tw, split, rowmap};
+    return {n, m, nslices, sl, cp, ci, bt, c16, btab, d64.vp, v64, d64.tid, tv64, d64.tw, split, rowmap};
   }
   DevSELLView<float> f() const {
-    return {n, m, nslices, sp, sl, ci, d32.vp, v32, d32.tid, tv32, d32.tw, split, rowmap};
+    return {n, m, nslices, sl, cp, ci, bt, c16, btab, d32.vp, v32, d32.tid, tv32, d32.tw, split, rowmap};
   }
 };
 
@@ -202,17 +205,26 @@ static DevCSR upload_csr(fvem_hierarchy *h, const HostCSR &A, bool f32, hipStrea
   return d;
 }
 
-static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, bool templates, hipStream_t s) {
-  HostSELL S = to_sell(A, templates);
+static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, bool templates, bool codes, hipStream_t s) {
+  HostSELL S = to_sell(A, templates, 64, 1024, codes);
   DevSELL d;
   d.n = S.n;
   d.m = S.m;
   d.nnz = S.nnz;
   d.nslices = S.nslices;
-  d.stored = S.sp.back();
-  d.sp = h->mem.upload(S.sp, s);
+  d.cp = h->mem.upload(S.cp, s);
+  d.bt = h->mem.upload(S.bt, s);
   d.sl = h->mem.upload(S.sl, s);
   d.ci = h->mem.upload(S.ci, s);
+  d.c16 = h->mem.upload(S.c16, s);
+  d.btab = h->mem.upload(S.btab, s);
+  d.n_ci = static_cast<int64_t>(S.ci.size());
+  d.n_c16 = static_cast<int64_t>(S.c16.size());
+  for (int64_t sl = 0; sl < S.nslices; ++sl) {
+    int64_t e = 0;
+    for (int64_t i = 64 * sl; i < std::min(S.n, 64 * sl + 64); ++i) e += S.rl[i];
+    d.col_bytes += S.bt[sl] >= 0 ? 2 * e + 256 : 4 * e;
+  }
   auto meta = [&](const HostValues &V, DevValues &D) {
     D.vp = h->mem.upload(V.vp, s);
     D.tid = h->mem.upload(V.tid, s);
@@ -238,6 +250,9 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, bool templates, 
     HIPCHECK(hipStreamSynchronize(s));   // before the temporaries and host arrays go
   }
   d.hsp = std::move(S.sp);
+  d.hcp = std::move(S.cp);
+  d.hbt = std::move(S.bt);
+  d.hbtab = std::move(S.btab);
   d.hsl = std::move(S.sl);
   d.hrl = std::move(S.rl);
   d.hv64 = std::move(S.v64);
@@ -532,8 +547,9 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   for (int l = 0; l < L; ++l) {
     Level &V = h->lv[l];
     V.n = A[l].n_rows;
-    V.A = upload_sell(h, A[l], true, s);
-    V.A.split = small_rows >= 0 && V.n <= small_rows;
+    const bool split = small_rows >= 0 && V.n <= small_rows;
+    V.A = upload_sell(h, A[l], true, !split, s);
+    V.A.split = split;
     std::vector<double> dinv(V.n);
     for (int64_t i = 0; i < V.n; ++i) {
       double d = 0.0;
@@ -551,9 +567,10 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
       // from templates where rows repeat; outputs are scattered back by rowmap
       auto transfer = [&](const HostCSR &T) {
         const std::vector<int32_t> ord = window_order(T, ORDER_WINDOW);
-        DevSELL d = upload_sell(h, permute(T, ord, nullptr), true, s);
+        const bool split = small_rows >= 0 && T.n_rows <= small_rows;
+        DevSELL d = upload_sell(h, permute(T, ord, nullptr), true, !split, s);
         d.rowmap = h->mem.upload(ord, s);
-        d.split = small_rows >= 0 && d.n <= small_rows;
+        d.split = split;
         HIPCHECK(hipStreamSynchronize(s));
         return d;
       };
@@ -1061,6 +1078,18 @@ fvem_status fvem_level_storage(fvem_hierarchy *h, int32_t level, int64_t *nnz, i
   return FVEM_OK;
 }
 
+fvem_status fvem_level_bytes(fvem_hierarchy *h, int32_t level, int32_t precision, int64_t *bytes) {
+  if (!h || level < 0 || level >= h->nlev || !bytes) {
+    g_last_error = "bad handle, level or output";
+    return FVEM_ERR_INVALID;
+  }
+  const DevSELL &A = h->lv[level].A;
+  const DevValues &V = precision == FVEM_PREC_FP64 ? A.d64 : A.d32;
+  const int64_t vb = precision == FVEM_PREC_FP64 ? 8 : 4;
+  *bytes = A.col_bytes + vb * V.nnz_explicit + 4 * V.rows_templated;
+  return FVEM_OK;
+}
+
 fvem_status fvem_hierarchy_cells(fvem_hierarchy *h, int64_t *n_cells) {
   if (!h || !n_cells) {
     g_last_error = "null argument";
@@ -1166,12 +1195,17 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
     S.nnz = A.nnz;
     S.nslices = A.nslices;
     S.sp = A.hsp;
+    S.cp = A.hcp;
+    S.bt = A.hbt;
+    S.btab = A.hbtab;
     S.sl = A.hsl;
     S.rl = A.hrl;
     S.v64 = A.hv64;
-    S.ci.resize(A.stored);
+    S.ci.resize(A.n_ci);
+    S.c16.resize(A.n_c16);
     S.v64.v.resize(A.d64.nvals);
-    HIPCHECK(hipMemcpy(S.ci.data(), A.ci, sizeof(int32_t) * A.stored, hipMemcpyDeviceToHost));
+    if (A.n_ci) HIPCHECK(hipMemcpy(S.ci.data(), A.ci, sizeof(int32_t) * A.n_ci, hipMemcpyDeviceToHost));
+    if (A.n_c16) HIPCHECK(hipMemcpy(S.c16.data(), A.c16, sizeof(uint16_t) * A.n_c16, hipMemcpyDeviceToHost));
     if (A.d64.nvals)
       HIPCHECK(hipMemcpy(S.v64.v.data(), A.v64, sizeof(double) * A.d64.nvals, hipMemcpyDeviceToHost));
     const std::vector<int32_t> &order = h->lv[level].order;

@@ -18,17 +18,22 @@ struct DevCSRView {
 };
 
 // Sliced ELLPACK with 64-row slices (one wavefront lane per row).  Slice s
-// holds rows [64 s, 64 s + 64); its columns are stored column-major, entry j
-// of lane r at ci[sp[s] + 64 j + r], for j < sl[s] (the longest row of the
-// slice).  Values: when vp[s] >= 0 at v[vp[s] + 64 j + r]; when vp[s] < 0
-// every row of the slice takes them from its template, tv[tid[row] * tw + j].
-// Shorter rows are padded with value 0 and a valid column.
+// holds rows [64 s, 64 s + 64); entry j of lane r sits at o = 256 (j / 4) +
+// 4 r + j % 4 from the slice's start, for j < sl[s] (the slice's longest row
+// rounded up to 4).  Columns: ci[cp[s] + o], or for coded slices (bt[s] >= 0)
+// btab[bt[s] + (c16[cp[s] + o] >> 10)] + (c16[cp[s] + o] & 1023).  Values:
+// when vp[s] >= 0 at v[vp[s] + o]; when vp[s] < 0 every row of the slice
+// takes them from its template, tv[tid[row] * tw + j].  Shorter rows are
+// padded with value 0 and a valid column.
 template <typename T>
 struct DevSELLView {
   int64_t n = 0, m = 0, nslices = 0;
-  const int64_t *sp = nullptr;
   const int32_t *sl = nullptr;
+  const int64_t *cp = nullptr;     // per slice: column offset in ci (bt < 0) or c16 (bt >= 0)
   const int32_t *ci = nullptr;
+  const int64_t *bt = nullptr;     // per slice: block-table offset in btab, or -1
+  const uint16_t *c16 = nullptr;   // 16-bit column codes (block index << 10 | offset)
+  const int32_t *btab = nullptr;   // block starts, 64 per coded slice
   const int64_t *vp = nullptr;
   const T *v = nullptr;
   const int32_t *tid = nullptr;

@@ -62,21 +62,43 @@ constexpr int SELL_GROUPS = 4;
 // of x share the CU's L1.
 constexpr int SELL_WAVES = 8;
 
-template <typename VT, typename XT, class Epi>
-__global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_t nslices, const int64_t *__restrict__ sp,
-                                                   const int32_t *__restrict__ sl, const int32_t *__restrict__ ci,
-                                                   const int64_t *__restrict__ vp, const VT *__restrict__ val,
-                                                   const int32_t *__restrict__ tid, const VT *__restrict__ tv,
-                                                   int32_t tw, const int32_t *__restrict__ rowmap,
-                                                   const XT *__restrict__ x, Epi epi) {
-  const int64_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int64_t slice = blk * SELL_WAVES + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (slice >= nslices) return;
-  using AT = typename Epi::acc_t;
-  const int groups = sl[slice] >> 2;
-  const int32_t *cp = ci + sp[slice] + 4 * lane;
-  const int64_t vb = vp[slice];
+typedef uint16_t ushort4v __attribute__((ext_vector_type(4)));
+
+// Column sources of a lane's group g (4 entries).  Plain: int32 columns.
+// Coded: 16-bit codes (block << 10 | offset); the slice's 64 block starts
+// sit one per lane of the wavefront and are fetched with a cross-lane read.
+struct ColsPlain {
+  const int32_t *cp;
+  __device__ int4v operator()(int g) const {
+    return __builtin_nontemporal_load(reinterpret_cast<const int4v *>(cp + 256 * static_cast<int64_t>(g)));
+  }
+};
+struct ColsCoded {
+  const uint16_t *cq;
+  int32_t tab;   // this lane's block start
+  __device__ int4v operator()(int g) const {
+    const ushort4v q = __builtin_nontemporal_load(reinterpret_cast<const ushort4v *>(cq + 256 * static_cast<int64_t>(g)));
+    int4v c;
+    c.x = __shfl(tab, q.x >> 10) + (q.x & 1023);
+    c.y = __shfl(tab, q.y >> 10) + (q.y & 1023);
+    c.z = __shfl(tab, q.z >> 10) + (q.z & 1023);
+    c.w = __shfl(tab, q.w >> 10) + (q.w & 1023);
+    return c;
+  }
+};
+// Value sources: stored with the slice (streamed) or a template row (cached).
+template <typename VT> struct ValsStored {
+  const VT *vq;
+  __device__ void operator()(int g, VT v[4]) const { Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g), v); }
+};
+template <typename VT> struct ValsTemplate {
+  const VT *tq;
+  __device__ void operator()(int g, VT v[4]) const { Quad<VT>::load(tq + 4 * g, v); }
+};
+
+// sum over a row's groups, SELL_GROUPS of them in flight
+template <typename AT, typename VT, typename XT, class Cols, class Vals>
+__device__ __forceinline__ AT row_sum(int groups, const Cols &cols, const Vals &vals, const XT *__restrict__ x) {
   AT acc = 0;
   auto fma4 = [&](const int4v c, const VT v[4]) {
     acc += static_cast<AT>(v[0]) * static_cast<AT>(x[c.x]);
@@ -84,50 +106,51 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_
     acc += static_cast<AT>(v[2]) * static_cast<AT>(x[c.z]);
     acc += static_cast<AT>(v[3]) * static_cast<AT>(x[c.w]);
   };
-  auto cols = [&](int g) { return __builtin_nontemporal_load(reinterpret_cast<const int4v *>(cp + 256 * static_cast<int64_t>(g))); };
-  if (vb >= 0) {
-    // values stored with the slice, in the same interleaved layout
-    const VT *vq = val + vb + 4 * lane;
-    int g = 0;
-    for (; g + SELL_GROUPS <= groups; g += SELL_GROUPS) {
-      int4v c[SELL_GROUPS];
-      VT v[SELL_GROUPS][4];
+  int g = 0;
+  for (; g + SELL_GROUPS <= groups; g += SELL_GROUPS) {
+    int4v c[SELL_GROUPS];
+    VT v[SELL_GROUPS][4];
 #pragma unroll
-      for (int u = 0; u < SELL_GROUPS; ++u) {
-        c[u] = cols(g + u);
-        Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g + u), v[u]);
-      }
+    for (int u = 0; u < SELL_GROUPS; ++u) {
+      c[u] = cols(g + u);
+      vals(g + u, v[u]);
+    }
 #pragma unroll
-      for (int u = 0; u < SELL_GROUPS; ++u) fma4(c[u], v[u]);
-    }
-    for (; g < groups; ++g) {
-      const int4v c0 = cols(g);
-      VT v0[4];
-      Quad<VT>::load_nt(vq + 256 * static_cast<int64_t>(g), v0);
-      fma4(c0, v0);
-    }
+    for (int u = 0; u < SELL_GROUPS; ++u) fma4(c[u], v[u]);
+  }
+  for (; g < groups; ++g) {
+    VT v0[4];
+    vals(g, v0);
+    fma4(cols(g), v0);
+  }
+  return acc;
+}
+
+template <typename VT, typename XT, class Epi>
+__global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(
+    int64_t n, int64_t nslices, const int32_t *__restrict__ sl, const int64_t *__restrict__ cpo,
+    const int32_t *__restrict__ ci, const int64_t *__restrict__ bt, const uint16_t *__restrict__ c16,
+    const int32_t *__restrict__ btab, const int64_t *__restrict__ vp, const VT *__restrict__ val,
+    const int32_t *__restrict__ tid, const VT *__restrict__ tv, int32_t tw, const int32_t *__restrict__ rowmap,
+    const XT *__restrict__ x, Epi epi) {
+  const int64_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t slice = blk * SELL_WAVES + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;   // whole wavefronts only: every lane below takes part in the cross-lane reads
+  using AT = typename Epi::acc_t;
+  const int groups = sl[slice] >> 2;
+  const int64_t co = cpo[slice] + 4 * lane;
+  const int64_t bto = bt[slice];
+  const int64_t vb = vp[slice];
+  AT acc;
+  if (bto >= 0) {
+    const ColsCoded cols{c16 + co, btab[bto + lane]};
+    if (vb >= 0) acc = row_sum<AT, VT>(groups, cols, ValsStored<VT>{val + vb + 4 * lane}, x);
+    else acc = row_sum<AT, VT>(groups, cols, ValsTemplate<VT>{tv + static_cast<int64_t>(tid[slice * 64 + lane]) * tw}, x);
   } else {
-    // every row of the slice repeats a template row: values come from the
-    // small template table (cache resident), only the columns stream
-    const VT *tq = tv + static_cast<int64_t>(tid[slice * 64 + lane]) * tw;
-    int g = 0;
-    for (; g + SELL_GROUPS <= groups; g += SELL_GROUPS) {
-      int4v c[SELL_GROUPS];
-      VT v[SELL_GROUPS][4];
-#pragma unroll
-      for (int u = 0; u < SELL_GROUPS; ++u) {
-        c[u] = cols(g + u);
-        Quad<VT>::load(tq + 4 * (g + u), v[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < SELL_GROUPS; ++u) fma4(c[u], v[u]);
-    }
-    for (; g < groups; ++g) {
-      const int4v c0 = cols(g);
-      VT v0[4];
-      Quad<VT>::load(tq + 4 * g, v0);
-      fma4(c0, v0);
-    }
+    const ColsPlain cols{ci + co};
+    if (vb >= 0) acc = row_sum<AT, VT>(groups, cols, ValsStored<VT>{val + vb + 4 * lane}, x);
+    else acc = row_sum<AT, VT>(groups, cols, ValsTemplate<VT>{tv + static_cast<int64_t>(tid[slice * 64 + lane]) * tw}, x);
   }
   const int64_t row = slice * 64 + lane;
   if (row < n) epi(rowmap ? static_cast<int64_t>(rowmap[row]) : row, acc);
@@ -141,14 +164,11 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(int64_t n, int64_
 constexpr int SELL_SPLIT = 16;
 
 template <typename VT, typename XT, class Epi>
-__global__ __launch_bounds__(256) void sell_split_kernel(int64_t n, const int64_t *__restrict__ sp,
-                                                         const int32_t *__restrict__ sl,
-                                                         const int32_t *__restrict__ ci,
-                                                         const int64_t *__restrict__ vp, const VT *__restrict__ val,
-                                                         const int32_t *__restrict__ tid,
-                                                         const VT *__restrict__ tv, int32_t tw,
-                                                         const int32_t *__restrict__ rowmap,
-                                                         const XT *__restrict__ x, Epi epi) {
+__global__ __launch_bounds__(256) void sell_split_kernel(
+    int64_t n, const int32_t *__restrict__ sl, const int64_t *__restrict__ cpo, const int32_t *__restrict__ ci,
+    const int64_t *__restrict__ bt, const uint16_t *__restrict__ c16, const int32_t *__restrict__ btab,
+    const int64_t *__restrict__ vp, const VT *__restrict__ val, const int32_t *__restrict__ tid,
+    const VT *__restrict__ tv, int32_t tw, const int32_t *__restrict__ rowmap, const XT *__restrict__ x, Epi epi) {
   const int64_t row = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / SELL_SPLIT;
   const int k = threadIdx.x % SELL_SPLIT;
   if (row >= n) return;
@@ -156,13 +176,24 @@ __global__ __launch_bounds__(256) void sell_split_kernel(int64_t n, const int64_
   const int64_t slice = row >> 6;
   const int q = static_cast<int>(row & 63);
   const int groups = sl[slice] >> 2;
-  const int32_t *cp = ci + sp[slice] + 4 * q;
+  const int64_t co = cpo[slice] + 4 * q;
+  const int64_t bto = bt[slice];
   const int64_t vb = vp[slice];
   const VT *vq = vb >= 0 ? val + vb + 4 * q : nullptr;
   const VT *tq = vb >= 0 ? nullptr : tv + static_cast<int64_t>(tid[row]) * tw;
   AT acc = 0;
   for (int g = k; g < groups; g += SELL_SPLIT) {
-    const int4v c = *reinterpret_cast<const int4v *>(cp + 256 * static_cast<int64_t>(g));
+    int4v c;
+    if (bto >= 0) {
+      // codes decoded through the slice's block table (cache resident)
+      const ushort4v u = *reinterpret_cast<const ushort4v *>(c16 + co + 256 * static_cast<int64_t>(g));
+      c.x = btab[bto + (u.x >> 10)] + (u.x & 1023);
+      c.y = btab[bto + (u.y >> 10)] + (u.y & 1023);
+      c.z = btab[bto + (u.z >> 10)] + (u.z & 1023);
+      c.w = btab[bto + (u.w >> 10)] + (u.w & 1023);
+    } else {
+      c = *reinterpret_cast<const int4v *>(ci + co + 256 * static_cast<int64_t>(g));
+    }
     VT v[4];
     if (vq) Quad<VT>::load(vq + 256 * static_cast<int64_t>(g), v);
     else Quad<VT>::load(tq + 4 * g, v);
@@ -181,13 +212,13 @@ static void launch_sell(const DevSELLView<VT> &A, const XT *x, Epi epi, hipStrea
   if (A.nslices == 0) return;
   if (A.split) {
     const dim3 grid(static_cast<unsigned>((A.n * SELL_SPLIT + 255) / 256));
-    sell_split_kernel<VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.sp, A.sl, A.ci, A.vp, A.v, A.tid, A.tv, A.tw,
-                                                        A.rowmap, x, epi);
+    sell_split_kernel<VT, XT, Epi><<<grid, 256, 0, s>>>(A.n, A.sl, A.cp, A.ci, A.bt, A.c16, A.btab, A.vp, A.v,
+                                                        A.tid, A.tv, A.tw, A.rowmap, x, epi);
     return;
   }
   const dim3 grid(static_cast<unsigned>((A.nslices + SELL_WAVES - 1) / SELL_WAVES));
-  sell_kernel<VT, XT, Epi><<<grid, 64 * SELL_WAVES, 0, s>>>(A.n, A.nslices, A.sp, A.sl, A.ci, A.vp, A.v, A.tid,
-                                                            A.tv, A.tw, A.rowmap, x, epi);
+  sell_kernel<VT, XT, Epi><<<grid, 64 * SELL_WAVES, 0, s>>>(A.n, A.nslices, A.sl, A.cp, A.ci, A.bt, A.c16, A.btab,
+                                                            A.vp, A.v, A.tid, A.tv, A.tw, A.rowmap, x, epi);
 }
 
 template <typename T>

@@ -334,7 +334,7 @@ void layout_values(const HostCSR &A, const std::vector<int64_t> &ord, const Host
 
 }  // namespace
 
-HostSELL to_sell(const HostCSR &A, bool templates, int min_uses, int max_templates) {
+HostSELL to_sell(const HostCSR &A, bool templates, int min_uses, int max_templates, bool codes) {
   HostSELL S;
   S.n = A.n_rows;
   S.m = A.n_cols;
@@ -365,7 +365,7 @@ HostSELL to_sell(const HostCSR &A, bool templates, int min_uses, int max_templat
   }
   layout_values(A, ord, S, S.v64, templates);
   layout_values(A, ord, S, S.v32, templates);
-  S.ci.assign(S.sp.back(), 0);
+  std::vector<int32_t> full(S.sp.back(), 0);
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < S.nslices; ++s)
     for (int r = 0; r < 64; ++r) {
@@ -373,9 +373,54 @@ HostSELL to_sell(const HostCSR &A, bool templates, int min_uses, int max_templat
       const int32_t pad = static_cast<int32_t>(std::min<int64_t>(std::min(i, S.n - 1), S.m - 1));
       for (int j = 0; j < S.sl[s]; ++j) {
         const bool real = i < S.n && j < S.rl[i];
-        S.ci[S.sp[s] + S.at(s, j, r)] = real ? A.ci[ord[A.rp[i] + j]] : (pad < 0 ? 0 : pad);
+        full[S.sp[s] + S.at(s, j, r)] = real ? A.ci[ord[A.rp[i] + j]] : (pad < 0 ? 0 : pad);
       }
     }
+  // column codes: the distinct 1024-column blocks of each slice
+  S.bt.assign(S.nslices, -1);
+  S.cp.assign(S.nslices, 0);
+  std::vector<std::vector<int32_t>> blocks(S.nslices);
+  if (codes) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < S.nslices; ++s) {
+      std::vector<int32_t> &b = blocks[s];
+      for (int64_t q = S.sp[s]; q < S.sp[s + 1]; ++q) b.push_back(full[q] >> 10);
+      std::sort(b.begin(), b.end());
+      b.erase(std::unique(b.begin(), b.end()), b.end());
+      if (b.size() > 64) b.clear();
+    }
+  }
+  int64_t n32 = 0, n16 = 0, nb = 0;
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    const int64_t len = S.sp[s + 1] - S.sp[s];
+    if (!blocks[s].empty()) {
+      S.bt[s] = nb;
+      nb += 64;
+      S.cp[s] = n16;
+      n16 += len;
+    } else {
+      S.cp[s] = n32;
+      n32 += len;
+    }
+  }
+  S.ci.assign(n32, 0);
+  S.c16.assign(n16, 0);
+  S.btab.assign(nb, 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    const int64_t len = S.sp[s + 1] - S.sp[s];
+    if (S.bt[s] < 0) {
+      std::copy(full.begin() + S.sp[s], full.begin() + S.sp[s] + len, S.ci.begin() + S.cp[s]);
+      continue;
+    }
+    const std::vector<int32_t> &b = blocks[s];
+    for (size_t k = 0; k < b.size(); ++k) S.btab[S.bt[s] + k] = b[k] << 10;
+    for (int64_t q = 0; q < len; ++q) {
+      const int32_t c = full[S.sp[s] + q];
+      const int64_t k = std::lower_bound(b.begin(), b.end(), c >> 10) - b.begin();
+      S.c16[S.cp[s] + q] = static_cast<uint16_t>((k << 10) | (c & 1023));
+    }
+  }
   return S;
 }
 
@@ -392,7 +437,7 @@ HostCSR from_sell(const HostSELL &S) {
     const int64_t s = i / 64;
     for (int j = 0; j < S.rl[i]; ++j) {
       const int64_t off = S.at(s, j, static_cast<int>(i % 64));
-      A.ci[A.rp[i] + j] = S.ci[S.sp[s] + off];
+      A.ci[A.rp[i] + j] = S.col(s, j, static_cast<int>(i % 64));
       A.v[A.rp[i] + j] = V.vp[s] >= 0 ? V.v[V.vp[s] + off] : V.tv[static_cast<size_t>(V.tid[i]) * V.tw + j];
     }
   }

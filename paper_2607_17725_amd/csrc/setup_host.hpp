@@ -87,17 +87,32 @@ struct HostValues {
   std::vector<double> tv;    // nt * tw template values
   int64_t nnz_explicit = 0, rows_templated = 0;
 };
+//
+// Column codes: a slice whose columns fall in at most 64 aligned blocks of
+// 1024 columns stores 16-bit codes (block index << 10 | offset in block) and
+// a 64-entry table of block starts; other slices store int32 columns.
 struct HostSELL {
   int64_t n = 0, m = 0, nnz = 0, nslices = 0;
-  std::vector<int64_t> sp;   // nslices + 1, column offsets (entries)
+  std::vector<int64_t> sp;   // nslices + 1, logical slice offsets (entries)
   std::vector<int32_t> sl;   // longest row per slice, rounded up to a multiple of 4
   std::vector<int32_t> rl;   // row lengths
-  std::vector<int32_t> ci;
+  std::vector<int64_t> cp;   // per slice: offset of its columns in ci (bt < 0) or c16 (bt >= 0)
+  std::vector<int64_t> bt;   // per slice: offset of its block table in btab, or -1
+  std::vector<int32_t> ci;   // int32 columns of the slices without codes
+  std::vector<uint16_t> c16; // column codes
+  std::vector<int32_t> btab; // block starts, 64 per coded slice
   HostValues v64, v32;       // exact (FP64) and single-precision value sets
   int64_t at(int64_t s, int j, int r) const { return 256 * static_cast<int64_t>(j >> 2) + 4 * r + (j & 3); }
+  int32_t col(int64_t s, int j, int r) const {
+    const int64_t o = cp[s] + at(s, j, r);
+    if (bt[s] < 0) return ci[o];
+    return btab[bt[s] + (c16[o] >> 10)] + (c16[o] & 1023);
+  }
 };
-// entries of every row ordered by (value, column) when templates are used
-HostSELL to_sell(const HostCSR &A, bool templates = false, int min_uses = 64, int max_templates = 1024);
+// entries of every row ordered by (value, column) when templates are used;
+// codes: 16-bit column codes where a slice's columns allow
+HostSELL to_sell(const HostCSR &A, bool templates = false, int min_uses = 64, int max_templates = 1024,
+                 bool codes = false);
 HostCSR from_sell(const HostSELL &S);   // FP64 values
 
 // max_i sum_j |a_ij| / sqrt(a_ii a_jj): Gershgorin bound of D^-1/2 A D^-1/2,

@@ -75,7 +75,7 @@ EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_app
            "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error", "fvem_grid_build",
            "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy",
            "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells",
-           "fvem_level_storage"]
+           "fvem_level_storage", "fvem_level_bytes"]
 
 _lib = None
 
@@ -106,6 +106,8 @@ def load(path=LIB_PATH):
     lib.fvem_level_storage.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fvem_level_storage.restype = ctypes.c_int
+    lib.fvem_level_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(i64)]
+    lib.fvem_level_bytes.restype = ctypes.c_int
     lib.fvem_hierarchy_cells.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fvem_hierarchy_cells.restype = ctypes.c_int
     lib.fvem_level_matrix.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
@@ -334,6 +336,12 @@ class Hierarchy:
         _check(load().fvem_level_storage(self._h, level, *[ctypes.byref(x) for x in v]))
         return dict(zip(("nnz", "nnz_explicit", "rows_templated", "n_templates", "template_width"),
                         (x.value for x in v)))
+
+    def level_bytes(self, level, precision=PREC_MIXED):
+        """Matrix bytes one application of level ``level``'s operator reads (see fvem_level_bytes)."""
+        b = ctypes.c_int64()
+        _check(load().fvem_level_bytes(self._h, level, precision, ctypes.byref(b)))
+        return b.value
 
     def level_matrix(self, level):
         """Level operator as (row_ptr, col, val) host arrays."""

@@ -72,6 +72,7 @@ int main() {
       ok = ok && S.sl[s] == ((mx + 3) & ~3);
     }
     for (int32_t c : S.ci) ok = ok && c >= 0 && c < A.n_cols;
+    ok = ok && S.c16.empty();
     // padding contributes zero: a dense product through the slices equals A x
     std::vector<double> x(A.n_cols), y(n, 0.0);
     for (auto &v : x) v = std::normal_distribution<double>()(g);
@@ -80,7 +81,7 @@ int main() {
         const int64_t i = s * 64 + r;
         if (i >= n) continue;
         for (int j = 0; j < S.sl[s]; ++j)
-          y[i] += S.v64.v[S.v64.vp[s] + S.at(s, j, r)] * x[S.ci[S.sp[s] + S.at(s, j, r)]];
+          y[i] += S.v64.v[S.v64.vp[s] + S.at(s, j, r)] * x[S.col(s, j, r)];
       }
     std::vector<double> yr(n, 0.0);
     for (int64_t i = 0; i < n; ++i)
@@ -91,6 +92,18 @@ int main() {
     char msg[96];
     std::snprintf(msg, sizeof msg, "sliced storage round trip, n=%lld", static_cast<long long>(n));
     expect(ok, msg);
+  }
+  // column codes on random rows: narrow column ranges code, wide ones do not
+  for (int64_t m : {3000, 400000}) {
+    HostCSR A = random_csr(g, 300, m, 70);
+    HostSELL S = to_sell(A, false, 64, 1024, true);
+    int coded = 0;
+    for (int64_t s2 = 0; s2 < S.nslices; ++s2) coded += S.bt[s2] >= 0;
+    const HostCSR B = from_sell(S);
+    char msg[96];
+    std::snprintf(msg, sizeof msg, "column codes round trip, %lld columns (%d of %lld slices coded)",
+                  static_cast<long long>(m), coded, static_cast<long long>(S.nslices));
+    expect(B.rp == A.rp && B.ci == A.ci && B.v == A.v && (m == 3000 ? coded == S.nslices : coded == 0), msg);
   }
   // value templates: a 7-point stencil on a 3-D grid (translation-invariant
   // interior rows, boundary rows differ) plus perturbed rows
@@ -119,7 +132,23 @@ int main() {
       }
       A.rp[i + 1] = static_cast<int64_t>(A.ci.size());
     }
-    HostSELL S = to_sell(A, true, 4);
+    HostSELL S = to_sell(A, true, 4, 1024, true);
+    {
+      // columns through the codes: the coded slices decode to what the
+      // uncoded storage holds
+      const HostSELL U = to_sell(A, true, 4, 1024, false);
+      int coded = 0;
+      bool same = true;
+      for (int64_t s2 = 0; s2 < S.nslices; ++s2) {
+        coded += S.bt[s2] >= 0;
+        for (int r = 0; r < 64; ++r)
+          for (int j = 0; j < S.sl[s2]; ++j) same = same && S.col(s2, j, r) == U.col(s2, j, r);
+      }
+      char m2[96];
+      std::snprintf(m2, sizeof m2, "16-bit column codes (%d of %lld slices coded)", coded,
+                    static_cast<long long>(S.nslices));
+      expect(same && coded > 0, m2);
+    }
     std::vector<double> x(n);
     for (auto &v : x) v = std::normal_distribution<double>()(gg);
     std::vector<double> yr(n, 0.0);
@@ -138,7 +167,7 @@ int main() {
           if (i >= n) continue;
           for (int j = 0; j < S.sl[s2]; ++j) {
             const double v = V.vp[s2] >= 0 ? V.v[V.vp[s2] + S.at(s2, j, r)] : V.tv[static_cast<size_t>(V.tid[i]) * V.tw + j];
-            y[i] += v * x[S.ci[S.sp[s2] + S.at(s2, j, r)]];
+            y[i] += v * x[S.col(s2, j, r)];
           }
         }
       // FP64 templates are exact: the diagonal's 1e-15 jitter splits them;

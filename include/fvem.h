@@ -134,7 +134,7 @@ typedef struct {
     double coarse_rcond;        /* pivots below rcond * diag are treated as zero [0] */
     double coarse_shift;        /* the coarsest level factors A_c + shift diag(A_c) [1e-8] */
     int64_t small_level_rows;   /* levels with at most this many rows share each row among 16
-                                   lanes instead of one lane per row [1048576]; < 0: never */
+                                   lanes instead of one lane per row [131072]; < 0: never */
 } fvem_options;
 
 typedef enum { FVEM_PREC_FP64 = 0, FVEM_PREC_MIXED = 1 } fvem_precision;

@@ -369,7 +369,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const int64_t dense_max = (o && o->coarse_dense_max > 0) ? o->coarse_dense_max : 16384;
   const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 0.0;
   const double shift = (o && o->coarse_shift > 0) ? o->coarse_shift : 1e-8;
-  const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 1048576;
+  const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 131072;
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
   h->lv.resize(L);
@@ -548,7 +548,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     Level &V = h->lv[l];
     V.n = A[l].n_rows;
     const bool split = small_rows >= 0 && V.n <= small_rows;
-    V.A = upload_sell(h, A[l], true, !split, s);
+    V.A = upload_sell(h, A[l], true, true, s);
     V.A.split = split;
     std::vector<double> dinv(V.n);
     for (int64_t i = 0; i < V.n; ++i) {
@@ -568,7 +568,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
       auto transfer = [&](const HostCSR &T) {
         const std::vector<int32_t> ord = window_order(T, ORDER_WINDOW);
         const bool split = small_rows >= 0 && T.n_rows <= small_rows;
-        DevSELL d = upload_sell(h, permute(T, ord, nullptr), true, !split, s);
+        DevSELL d = upload_sell(h, permute(T, ord, nullptr), true, true, s);
         d.rowmap = h->mem.upload(ord, s);
         d.split = split;
         HIPCHECK(hipStreamSynchronize(s));

@@ -35,11 +35,11 @@ def log(msg):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sell_cheb_plates128_traffic.json")
 LAYOUT_SOURCES = [os.path.join(ROOT, "paper_2607_17725_amd", "csrc", f)
-                  for f in ("sell.hip", "epilogues.hpp", "setup_host.cpp")]
+                  for f in ("sell.hip", "epilogues.hpp", "setup_host.cpp", "api.hip")]
 
 
 def layout_hash():
-    """sha256 over the kernel and data-layout sources the counter figures depend on."""
+    """sha256 over the kernel, data-layout and option-default sources the counter figures depend on."""
     import hashlib
     h = hashlib.sha256()
     for f in LAYOUT_SOURCES:
@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-N", type=int, default=16)
     ap.add_argument("--rhs", type=int, default=16, help="right-hand sides per step (profiling runs use fewer)")
+    ap.add_argument("--max-templates", type=int, default=0,
+                    help="value templates per operator (0: library default, <0: none)")
     ap.add_argument("--small-level-rows", type=int, default=0,
                     help="levels up to this many rows use the row-split SpMV (0: library default, <0: never)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -144,7 +146,8 @@ def main():
     log(f"grid built in {t_grid:.1f} s: {grid.n_dof} DOFs, {grid.n_vert} vertices, {grid.n_trees} cut cells")
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    hier = fvem.Hierarchy(grid, stream=stream, small_level_rows=args.small_level_rows)
+    hier = fvem.Hierarchy(grid, stream=stream, small_level_rows=args.small_level_rows,
+                          max_templates=args.max_templates)
     torch.cuda.synchronize()
     t_hier = time.perf_counter() - t0
     n0 = hier.n_dof

@@ -135,6 +135,7 @@ typedef struct {
     double coarse_shift;        /* the coarsest level factors A_c + shift diag(A_c) [1e-8] */
     int64_t small_level_rows;   /* levels with at most this many rows share each row among 16
                                    lanes instead of one lane per row [131072]; < 0: never */
+    int32_t max_templates;      /* value templates per operator [4096]; < 0: none */
 } fvem_options;
 
 typedef enum { FVEM_PREC_FP64 = 0, FVEM_PREC_MIXED = 1 } fvem_precision;

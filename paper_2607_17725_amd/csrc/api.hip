@@ -205,8 +205,8 @@ static DevCSR upload_csr(fvem_hierarchy *h, const HostCSR &A, bool f32, hipStrea
   return d;
 }
 
-static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, bool templates, bool codes, hipStream_t s) {
-  HostSELL S = to_sell(A, templates, 64, 1024, codes);
+static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_templates, bool codes, hipStream_t s) {
+  HostSELL S = to_sell(A, max_templates > 0, 64, std::max(max_templates, 1), codes);
   DevSELL d;
   d.n = S.n;
   d.m = S.m;
@@ -370,6 +370,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 0.0;
   const double shift = (o && o->coarse_shift > 0) ? o->coarse_shift : 1e-8;
   const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 131072;
+  const int max_templates = (o && o->max_templates != 0) ? o->max_templates : 4096;
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
   h->lv.resize(L);
@@ -548,7 +549,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     Level &V = h->lv[l];
     V.n = A[l].n_rows;
     const bool split = small_rows >= 0 && V.n <= small_rows;
-    V.A = upload_sell(h, A[l], true, true, s);
+    V.A = upload_sell(h, A[l], max_templates, true, s);
     V.A.split = split;
     std::vector<double> dinv(V.n);
     for (int64_t i = 0; i < V.n; ++i) {
@@ -568,7 +569,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
       auto transfer = [&](const HostCSR &T) {
         const std::vector<int32_t> ord = window_order(T, ORDER_WINDOW);
         const bool split = small_rows >= 0 && T.n_rows <= small_rows;
-        DevSELL d = upload_sell(h, permute(T, ord, nullptr), true, true, s);
+        DevSELL d = upload_sell(h, permute(T, ord, nullptr), max_templates, true, s);
         d.rowmap = h->mem.upload(ord, s);
         d.split = split;
         HIPCHECK(hipStreamSynchronize(s));

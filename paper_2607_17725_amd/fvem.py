@@ -54,7 +54,8 @@ class _Grid(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("cheb_degree", ctypes.c_int32), ("cheb_lower", ctypes.c_double),
                 ("coarse_dense_max", ctypes.c_int32), ("coarse_rcond", ctypes.c_double),
-                ("coarse_shift", ctypes.c_double), ("small_level_rows", ctypes.c_int64)]
+                ("coarse_shift", ctypes.c_double), ("small_level_rows", ctypes.c_int64),
+                ("max_templates", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -159,7 +160,7 @@ class Hierarchy:
     """
 
     def __init__(self, desc, stream=None, cheb_degree=5, cheb_lower=1.0 / 30.0, coarse_dense_max=16384,
-                 coarse_rcond=0.0, coarse_shift=1e-8, small_level_rows=0):
+                 coarse_rcond=0.0, coarse_shift=1e-8, small_level_rows=0, max_templates=0):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -168,7 +169,7 @@ class Hierarchy:
             g = _Grid()
             _check(lib.fvem_grid_describe(desc._g, ctypes.byref(g)))
             self._finish(lib, g, [desc], stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond,
-                         coarse_shift, small_level_rows)
+                         coarse_shift, small_level_rows, max_templates)
             return
         keep = []
         L = len(desc["levels"])
@@ -209,12 +210,13 @@ class Hierarchy:
         g.n_vert = int(desc.get("n_vert", 0))
         g.n_components = int(desc.get("n_components", 0))
         self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                     small_level_rows)
+                     small_level_rows, max_templates)
 
     def _finish(self, lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                small_level_rows):
+                small_level_rows, max_templates):
         import torch
-        opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift, small_level_rows)
+        opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift, small_level_rows,
+                        max_templates)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         _check(lib.fvem_hierarchy_build(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),

@@ -343,6 +343,7 @@ static void build_velocity(fvem_hierarchy *h, const fvem_grid_desc *g, const Hos
   h->Av = upload_csr(h, transpose(AvT), false, s);
   h->vs1 = h->mem.alloc<double>(12 * nc);
   h->vs2 = h->mem.alloc<double>(12 * nc);
+  progress("hierarchy: velocity operators stored");
 }
 
 static void cheb_coefficients(Level &L, int deg, double lower) {
@@ -543,6 +544,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   }
   h->perm0 = h->mem.upload(h->lv[0].order, s);
   h->iperm0 = h->mem.upload(inv[0], s);
+  progress("hierarchy: level order and renumbering done");
 
   // upload
   for (int l = 0; l < L; ++l) {
@@ -578,6 +580,8 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
       V.P = transfer(P[l]);
       V.R = transfer(transpose(P[l]));
     }
+    progress("hierarchy: level %d stored (%lld of %lld rows templated)", l,
+             static_cast<long long>(V.A.d32.rows_templated), static_cast<long long>(V.n));
     V.b64 = h->mem.alloc<double>(V.n);
     V.x64 = h->mem.alloc<double>(V.n);
     V.xb64 = h->mem.alloc<double>(V.n);
@@ -593,6 +597,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   if (g->n_vert > 0) {
     h->B = upload_csr(h, Bh, false, s);
     h->BT = upload_csr(h, transpose(Bh), false, s);
+    progress("hierarchy: divergence stored");
   }
   h->comp0 = h->mem.upload(comp0, s);
   if (g->vc_off) build_velocity(h, g, c0, inv[0], s);

@@ -166,21 +166,45 @@ HostBlocks galerkin_blocks(const HostCells &fine, const HostBlocks &kf, const in
 }
 
 HostCSR transpose(const HostCSR &A) {
+  // each thread owns a contiguous range of rows; per-thread column counts
+  // give every (thread, column) pair its own write position, so the rows of
+  // each transposed row come out in increasing order, as a serial pass would
   HostCSR T;
   T.n_rows = A.n_cols;
   T.n_cols = A.n_rows;
-  T.rp.assign(T.n_rows + 1, 0);
-  for (int64_t k = 0; k < A.nnz(); ++k) T.rp[A.ci[k] + 1]++;
-  for (int64_t i = 0; i < T.n_rows; ++i) T.rp[i + 1] += T.rp[i];
-  T.ci.resize(A.nnz());
-  T.v.resize(A.nnz());
-  std::vector<int64_t> fill(T.rp.begin(), T.rp.end() - 1);
-  for (int64_t i = 0; i < A.n_rows; ++i)
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      int64_t dst = fill[A.ci[k]]++;
-      T.ci[dst] = static_cast<int32_t>(i);
-      T.v[dst] = A.v[k];
+  const int64_t n = A.n_rows, m = A.n_cols, nnz = A.nnz();
+  const int nt = std::max(1, std::min<int>(omp_get_max_threads(), static_cast<int>((nnz >> 20) + 1)));
+  std::vector<int64_t> lo(nt + 1);
+  for (int t = 0; t <= nt; ++t) lo[t] = n * t / nt;
+  std::vector<std::vector<int64_t>> pos(nt, std::vector<int64_t>(m, 0));
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+  for (int t = 0; t < nt; ++t)
+    for (int64_t k = A.rp[lo[t]]; k < A.rp[lo[t + 1]]; ++k) pos[t][A.ci[k]]++;
+  T.rp.assign(m + 1, 0);
+  for (int64_t c = 0; c < m; ++c) {
+    int64_t tot = 0;
+    for (int t = 0; t < nt; ++t) tot += pos[t][c];
+    T.rp[c + 1] = T.rp[c] + tot;
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < m; ++c) {
+    int64_t at = T.rp[c];
+    for (int t = 0; t < nt; ++t) {
+      const int64_t k = pos[t][c];
+      pos[t][c] = at;
+      at += k;
     }
+  }
+  T.ci.resize(nnz);
+  T.v.resize(nnz);
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+  for (int t = 0; t < nt; ++t)
+    for (int64_t i = lo[t]; i < lo[t + 1]; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int64_t dst = pos[t][A.ci[k]]++;
+        T.ci[dst] = static_cast<int32_t>(i);
+        T.v[dst] = A.v[k];
+      }
   return T;
 }
 
@@ -219,7 +243,8 @@ HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t r = 0; r < B.n_rows; ++r) {
     const int64_t o = order[r], len = A.rp[o + 1] - A.rp[o];
-    std::vector<std::pair<int32_t, double>> e(len);
+    thread_local std::vector<std::pair<int32_t, double>> e;
+    e.resize(len);
     for (int64_t q = 0; q < len; ++q) {
       const int32_t c = A.ci[A.rp[o] + q];
       e[q] = {col_map ? (*col_map)[c] : c, A.v[A.rp[o] + q]};

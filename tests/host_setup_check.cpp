@@ -248,6 +248,30 @@ int main() {
       for (int64_t j = 0; j < 170; ++j) ok = ok && DA[i * 170 + j] == DT[j * 300 + i];
     expect(ok, "transpose");
   }
+  // multithreaded transpose (several million nonzeros) against a serial
+  // counting-sort transpose: same arrays, rows ascending in every column
+  {
+    HostCSR A = random_csr(g, 200000, 50000, 40);
+    HostCSR T = transpose(A);
+    HostCSR R;
+    R.n_rows = A.n_cols;
+    R.n_cols = A.n_rows;
+    R.rp.assign(R.n_rows + 1, 0);
+    for (int64_t k = 0; k < A.nnz(); ++k) R.rp[A.ci[k] + 1]++;
+    for (int64_t c = 0; c < R.n_rows; ++c) R.rp[c + 1] += R.rp[c];
+    R.ci.resize(A.nnz());
+    R.v.resize(A.nnz());
+    std::vector<int64_t> fill(R.rp.begin(), R.rp.end() - 1);
+    for (int64_t i = 0; i < A.n_rows; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        R.ci[fill[A.ci[k]]] = static_cast<int32_t>(i);
+        R.v[fill[A.ci[k]]++] = A.v[k];
+      }
+    char msg[96];
+    std::snprintf(msg, sizeof msg, "transpose of %lld nonzeros matches the serial one",
+                  static_cast<long long>(A.nnz()));
+    expect(T.rp == R.rp && T.ci == R.ci && T.v == R.v, msg);
+  }
   // block assembly and element-wise Galerkin product against dense sums
   {
     const int nf = 40, nc = 12, ncell_f = 18, ncell_c = 4, mf = 6, mc = 5;

@@ -284,6 +284,8 @@ static void build_velocity(fvem_hierarchy *h, const fvem_grid_desc *g, const Hos
     check(g->cell_geom[5 * c + 3] > 0 && g->cell_geom[5 * c + 4] > 0, "cell diameter or volume not positive");
     for (int64_t q = g->cell_vptr[c]; q < g->cell_vptr[c + 1]; ++q) W[g->cell_vert[q]] += g->cell_geom[5 * c + 4];
   }
+  // rows 12 E + 4 c + a of cell E: lengths per cell, offsets, then a
+  // parallel fill (each cell writes only its own rows)
   HostCSR Pi, Gr, Ms, AvT;
   for (HostCSR *A : {&Pi, &Gr, &Ms, &AvT}) {
     A->n_rows = 12 * nc;
@@ -293,43 +295,53 @@ static void build_velocity(fvem_hierarchy *h, const fvem_grid_desc *g, const Hos
   Gr.n_cols = h->n0;
   Ms.n_cols = 12 * nc;
   AvT.n_cols = 3 * nv;
-  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t nvE = g->cell_vptr[c + 1] - g->cell_vptr[c];
+    int64_t nfree = 0;
+    for (int64_t q = c0.ptr[c]; q < c0.ptr[c + 1]; ++q) nfree += c0.dof[q] >= 0;
+    for (int r = 0; r < 12; ++r) {
+      const int64_t i = 12 * c + r;
+      Pi.rp[i + 1] = Pi.rp[i] + nvE;
+      Gr.rp[i + 1] = Gr.rp[i] + nfree;
+      Ms.rp[i + 1] = Ms.rp[i] + 4;
+      AvT.rp[i + 1] = AvT.rp[i] + nvE;
+    }
+  }
+  for (HostCSR *A : {&Pi, &Gr, &Ms, &AvT}) {
+    A->ci.resize(A->rp.back());
+    A->v.resize(A->rp.back());
+  }
+#pragma omp parallel for schedule(dynamic, 256)
   for (int64_t c = 0; c < nc; ++c) {
     const int64_t v0 = g->cell_vptr[c], nvE = g->cell_vptr[c + 1] - v0, nE = c0.ptr[c + 1] - c0.ptr[c];
     const double *blk = g->vc_val + g->vc_off[c];
     const double *pi1 = blk, *gk = blk + 4 * nvE, *m1 = blk + 4 * nvE + 12 * nE;
     const double *geo = g->cell_geom + 5 * c;
+    std::vector<std::pair<int32_t, int32_t>> fr;   // (level-order column, local slot)
+    for (int64_t q = 0; q < nE; ++q) {
+      const int32_t d = c0.dof[c0.ptr[c] + q];
+      if (d >= 0) fr.emplace_back(inv0[d], static_cast<int32_t>(q));
+    }
+    std::sort(fr.begin(), fr.end());
     for (int comp = 0; comp < 3; ++comp)
       for (int a = 0; a < 4; ++a) {
         const int64_t r = 12 * c + 4 * comp + a;
         for (int64_t v = 0; v < nvE; ++v) {
-          Pi.ci.push_back(3 * g->cell_vert[v0 + v] + comp);
-          Pi.v.push_back(pi1[a * nvE + v]);
-        }
-        Pi.rp[r + 1] = static_cast<int64_t>(Pi.ci.size());
-        row.clear();
-        for (int64_t q = 0; q < nE; ++q) {
-          const int32_t d = c0.dof[c0.ptr[c] + q];
-          if (d >= 0) row.emplace_back(inv0[d], gk[(comp * 4 + a) * nE + q]);
-        }
-        std::sort(row.begin(), row.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
-        for (const auto &e : row) {
-          Gr.ci.push_back(e.first);
-          Gr.v.push_back(e.second);
-        }
-        Gr.rp[r + 1] = static_cast<int64_t>(Gr.ci.size());
-        for (int b = 0; b < 4; ++b) {
-          Ms.ci.push_back(static_cast<int32_t>(12 * c + 4 * comp + b));
-          Ms.v.push_back(m1[a * 4 + b]);
-        }
-        Ms.rp[r + 1] = static_cast<int64_t>(Ms.ci.size());
-        for (int64_t v = 0; v < nvE; ++v) {
           const int32_t gv = g->cell_vert[v0 + v];
+          Pi.ci[Pi.rp[r] + v] = 3 * gv + comp;
+          Pi.v[Pi.rp[r] + v] = pi1[a * nvE + v];
           const double za = a == 0 ? 1.0 : (g->vert_xyz[3 * gv + a - 1] - geo[a - 1]) / geo[3];
-          AvT.ci.push_back(3 * gv + comp);
-          AvT.v.push_back(geo[4] / W[gv] * za);
+          AvT.ci[AvT.rp[r] + v] = 3 * gv + comp;
+          AvT.v[AvT.rp[r] + v] = geo[4] / W[gv] * za;
         }
-        AvT.rp[r + 1] = static_cast<int64_t>(AvT.ci.size());
+        for (size_t q = 0; q < fr.size(); ++q) {
+          Gr.ci[Gr.rp[r] + q] = fr[q].first;
+          Gr.v[Gr.rp[r] + q] = gk[(comp * 4 + a) * nE + fr[q].second];
+        }
+        for (int b2 = 0; b2 < 4; ++b2) {
+          Ms.ci[Ms.rp[r] + b2] = static_cast<int32_t>(12 * c + 4 * comp + b2);
+          Ms.v[Ms.rp[r] + b2] = m1[a * 4 + b2];
+        }
       }
   }
   check(12 * nc < (int64_t(1) << 31) && 3 * nv < (int64_t(1) << 31), "cell field too large for int32 columns");

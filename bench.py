@@ -112,7 +112,8 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--N", type=int, default=None, help="background resolution override")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--fp64-reference", action="store_true", help="also time the plain FP64 MG-PCG")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="skip the untimed-for-value comparisons (plain FP64 MG-PCG, adjoint solves)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-N", type=int, default=16)
     ap.add_argument("--rhs", type=int, default=16, help="right-hand sides per step (profiling runs use fewer)")
@@ -210,7 +211,10 @@ def main():
         f"= {achieved:.0f} GB/s")
 
     extra = {}
-    if args.fp64_reference:
+    if not args.no_reference:
+        # beside the value: the same right-hand sides through the plain FP64
+        # MG-PCG, and the adjoint solve (B^T K^+ of a seeded pressure
+        # sensitivity) in the benchmark's precision, both to the same tolerance
         prec_save = prec
         prec = fvem.PREC_FP64
         torch.cuda.synchronize()
@@ -220,8 +224,21 @@ def main():
         d64 = time.perf_counter() - t1
         prec = prec_save
         extra["fp64_reference"] = {"solves_per_s": len(U) / d64,
-                                   "iterations": [s["iterations"] for s in st64]}
+                                   "iterations": [s["iterations"] for s in st64],
+                                   "max_rel_residual": max(s["rel_residual"] for s in st64)}
         log(f"FP64 reference: {len(U) / d64:.3f} solves/s")
+        G = [torch.as_tensor(np.random.default_rng(500 + k).standard_normal(n0), device="cuda")
+             for k in range(len(U))]
+        gu = torch.empty(3 * grid.n_vert, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sta = [hier.solve_adjoint(gp, out=gu, tol=w.tol, precision=prec)[1] for gp in G]
+        torch.cuda.synchronize()
+        dad = time.perf_counter() - t1
+        extra["adjoint"] = {"solves_per_s": len(G) / dad, "iterations": [s["iterations"] for s in sta],
+                            "max_rel_residual": max(s["rel_residual"] for s in sta),
+                            "input": "N(0,1) pressure sensitivities, seeds 500+"}
+        log(f"adjoint: {len(G) / dad:.3f} solves/s")
 
     cpu = None
     if not args.no_cpu_baseline:

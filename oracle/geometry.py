@@ -45,10 +45,17 @@ MIN_VOLUME = 1e-12
 # --------------------------------------------------------------------------- polygons
 
 def polygon_area_vec(P):
-    Q = np.roll(P, -1, axis=0)
-    return 0.5 * np.stack([P[:, 1] * Q[:, 2] - P[:, 2] * Q[:, 1],
-                           P[:, 2] * Q[:, 0] - P[:, 0] * Q[:, 2],
-                           P[:, 0] * Q[:, 1] - P[:, 1] * Q[:, 0]], -1).sum(0)
+    """Vector area (1/2) sum_i p_i x p_{i+1}, with positions taken about p_0.
+
+    The shift leaves the sum unchanged in exact arithmetic; in floating point
+    it keeps a face much smaller than its distance from the origin from
+    cancelling to zero.
+    """
+    R = P - P[0]
+    Q = np.roll(R, -1, axis=0)
+    return 0.5 * np.stack([R[:, 1] * Q[:, 2] - R[:, 2] * Q[:, 1],
+                           R[:, 2] * Q[:, 0] - R[:, 0] * Q[:, 2],
+                           R[:, 0] * Q[:, 1] - R[:, 1] * Q[:, 0]], -1).sum(0)
 
 
 def polygon_area(P):

@@ -6,9 +6,11 @@
 namespace fvem::geo {
 
 V3 area_vector(const Polygon &P) {
+  // fan about the first vertex: relative positions keep tiny faces far from
+  // the origin exact instead of cancelling to zero
   V3 s;
   const size_t m = P.size();
-  for (size_t i = 0; i < m; ++i) s = s + cross(P[i], P[(i + 1) % m]);
+  for (size_t i = 1; i + 1 < m; ++i) s = s + cross(P[i] - P[0], P[i + 1] - P[0]);
   return 0.5 * s;
 }
 

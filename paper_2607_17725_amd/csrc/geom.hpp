@@ -38,7 +38,7 @@ struct Facet {       // planar convex facet, counter-clockwise about the outward
 };
 using Polyhedron = std::vector<Facet>;
 
-V3 area_vector(const Polygon &P);   // (1/2) sum p_i x p_{i+1}
+V3 area_vector(const Polygon &P);   // (1/2) sum (p_i - p_0) x (p_{i+1} - p_0)
 double area(const Polygon &P);
 // part of P with n.x <= d (+tol)
 Polygon clip(const Polygon &P, V3 n, double d, double tol = 1e-12);

@@ -25,6 +25,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <omp.h>
@@ -1235,6 +1237,31 @@ struct BuilderImpl {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t c = 0; c < nc; ++c)
       if (tmpl[c] < 0) data[c] = vem::element(vem_cell(M, c), k, true);
+    // a degenerate cell (e.g. a sliver edge far below the grid spacing) must
+    // not pass unnoticed into the operators
+    for (int64_t c = 0; c < nc; ++c) {
+      if (tmpl[c] >= 0) continue;
+      bool ok = true;
+      for (double v : data[c].K) ok = ok && std::isfinite(v);
+      for (double v : data[c].B) ok = ok && std::isfinite(v);
+      for (double v : data[c].V) ok = ok && std::isfinite(v);
+      if (ok) continue;
+      if (const char *dump = std::getenv("FVEM_DUMP_CELL")) {
+        // outward faces as vertex cycles, for offline inspection
+        const vem::Cell C = vem_cell(M, c);
+        if (FILE *fp = std::fopen(dump, "w")) {
+          std::fprintf(fp, "%zu %zu\n", C.X.size(), C.faces.size());
+          for (const V3 &x : C.X) std::fprintf(fp, "%.17g %.17g %.17g\n", x.x, x.y, x.z);
+          for (const auto &f : C.faces) {
+            std::fprintf(fp, "%zu", f.size());
+            for (int q : f) std::fprintf(fp, " %d", q);
+            std::fprintf(fp, "\n");
+          }
+          std::fclose(fp);
+        }
+      }
+      throw std::runtime_error("the VEM operators of cell " + std::to_string(c) + " are not finite");
+    }
     for (int64_t c = 0; c < nc; ++c) {
       const int64_t src = tmpl[c] < 0 ? c : tmpl[c];
       if (src == c) {

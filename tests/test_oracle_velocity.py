@@ -90,7 +90,13 @@ def test_gradient_velocity_is_removed(fx, request):
     # sliver cells (thickness below 1e-3 h_E) only pin the centroid value,
     # as in the gradient-operator pin above
     thin = np.array([g.basis.s.min() / g.hc <= 1e-3 for (gd, verts, em, g) in pb.asm.cells])
-    assert S[~thin].max() < 1e-8 * scale
+    # the pressure solve inside the projection carries the rounding of the
+    # whole grid: on the thin sheet its sliver cells (thickness ~1e-5 h_E)
+    # lift that floor to a few 1e-8 in the neighbouring cells, and a change
+    # of summation order alone moves it by a factor 5; a missing or wrong
+    # term leaves O(1) velocities
+    bar = 1e-8 if fx == "c3_small" else 1e-7
+    assert S[~thin].max() < bar * scale
     assert S[:, :, 0].max() < 1e-6 * scale
     assert thin.sum() == 0 or fx == "c4_small"
 

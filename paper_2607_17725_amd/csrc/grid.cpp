@@ -46,7 +46,10 @@ namespace {
 
 constexpr double kMinVolume = 1e-12;
 constexpr double kPlaneTol = 1e-12;
-constexpr double kVertTol = 1e-12;
+// vertices closer than this are one vertex: the same intersection reached
+// through different clipping sequences can differ by ~1e-12 where nearly
+// parallel planes meet; distinct vertices of the scenes stay above 1e-9
+constexpr double kVertTol = 1e-10;
 
 struct Node {
   Polyhedron poly;
@@ -487,7 +490,7 @@ struct BuilderImpl {
         }
         return v;
       }
-      const double q = 1e-10;
+      const double q = kVertTol;   // bucket width: a weld partner lies in a neighbouring bucket
       const int64_t bx = static_cast<int64_t>(std::floor(p.x / q)), by = static_cast<int64_t>(std::floor(p.y / q)),
                     bz = static_cast<int64_t>(std::floor(p.z / q));
       auto key = [](int64_t a, int64_t b, int64_t c) {

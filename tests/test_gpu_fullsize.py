@@ -1,6 +1,9 @@
-"""Properties of the 128^3 tilted-plates workload in the benchmark's launch configuration.
+"""Properties of the 128^3 workloads in the benchmark's launch configuration.
 
-The oracle cannot build this grid, so the checks hold at any size:
+The tilted plates (the benchmark's workload) and the curved thin sheet; the
+sheet's hierarchy build also runs the parent-cell test of every
+prolongation row (a row reaching outside its cell's parent is refused).
+The oracle cannot build these grids, so the checks hold at any size:
 * sampled rows of the assembled K (the sliced, templated FP64 operator the
   outer CG applies) equal the sum of the builder's element blocks, row by row;
 * K annihilates constants (pure Neumann, Sec. 3.1);
@@ -17,28 +20,39 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def plates128():
+# K 1 against the largest |K x|: the sheet's 1e-5-thin elements annihilate
+# constants to ~1e-9 of their row sums (measured on the host from the
+# element blocks), the plates' to ~1e-11; a missing contribution shows at O(1)
+_CONST_BAR = {"c3": 1e-9, "c4": 1e-7}
+# patch test: the sheet's pressure solve is far worse conditioned, so its
+# 1e-10 residual leaves a larger pressure error
+_PATCH_BAR = {"c3": 1e-6, "c4": 1e-4}
+
+
+@pytest.fixture(scope="module", params=["c3", "c4"])
+def grid128(request):
     import synth
     from paper_2607_17725_amd import fvem
     if not torch.cuda.is_available():
         pytest.fail("GPU tests need a GPU")
-    w = synth.get_config("c3", N=128)
+    w = synth.get_config(request.param, N=128)
     V, F = w.mesh()
-    print("[gpu fullsize] building the 128^3 plates grid", flush=True)
+    print(f"[gpu fullsize] building the 128^3 grid of {request.param}", flush=True)
     g = fvem.Grid(V, F, w.N, w.k, w.levels, w.dirichlet_top)
     print("[gpu fullsize] building the hierarchy", flush=True)
     h = fvem.Hierarchy(g)
-    return g, h
+    yield request.param, g, h
+    del h, g
+    torch.cuda.empty_cache()
 
 
 def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
 
 
-def test_sampled_rows_of_K(plates128):
+def test_sampled_rows_of_K(grid128):
     from paper_2607_17725_amd import fvem
-    g, h = plates128
+    _, g, h = grid128
     d = g.describe()
     lv = d["levels"][0]
     cp, cd = lv["cell_ptr"], lv["cell_dof"]
@@ -61,17 +75,17 @@ def test_sampled_rows_of_K(plates128):
         assert np.abs(col - ref).max() <= 1e-13 * np.abs(ref).max(), f"row {i}"
 
 
-def test_constants_and_symmetry(plates128):
+def test_constants_and_symmetry(grid128):
     from paper_2607_17725_amd import fvem
-    g, h = plates128
+    name, g, h = grid128
     one = torch.ones(h.n_dof, dtype=torch.float64, device="cuda")
     k1 = h.apply(fvem.OP_K, one)
     x = _dev(np.random.default_rng(1).standard_normal(h.n_dof))
     kx = h.apply(fvem.OP_K, x)
     # element blocks of sliver cut cells annihilate constants only to the
-    # rounding of their ill-conditioned local projections (~1e-11 here);
-    # a missing or misplaced contribution would show at O(1)
-    assert float(k1.abs().max()) <= 1e-9 * float(kx.abs().max())
+    # rounding of their ill-conditioned local projections
+    print(f"[gpu fullsize] {name}: max|K 1| / max|K x| = {float(k1.abs().max()) / float(kx.abs().max()):.2e}")
+    assert float(k1.abs().max()) <= _CONST_BAR[name] * float(kx.abs().max())
     xp = h.apply(fvem.OP_PROJECT, x)
     yp = h.apply(fvem.OP_PROJECT, _dev(np.random.default_rng(2).standard_normal(h.n_dof)))
     mx = h.apply(fvem.OP_VCYCLE, xp)
@@ -81,19 +95,20 @@ def test_constants_and_symmetry(plates128):
     assert abs(a - b) <= 1e-6 * abs(float(torch.dot(mx, xp)))
 
 
-def test_patch_test_solve(plates128):
-    g, h = plates128
+def test_patch_test_solve(grid128):
+    name, g, h = grid128
     rng = np.random.default_rng(3)
     A = rng.standard_normal((3, 3))
     A = A + A.T
     c = rng.standard_normal(3)
     X = g.vertices
     u = (X @ A + c[None, :]).ravel()                   # grad of q = 0.5 x^T A x + c.x
-    p, st = h.solve(_dev(u), tol=1e-10, precision=1, maxit=1000)
-    print(f"[gpu fullsize] patch test: {st['iterations']} iterations, residual {st['rel_residual']:.2e}")
+    p, st = h.solve(_dev(u), tol=1e-10, precision=1, maxit=2000)
+    print(f"[gpu fullsize] {name} patch test: {st['iterations']} iterations, residual {st['rel_residual']:.2e}")
     p = p.cpu().numpy()
     vert = g.dof_kind == 0
     xv = g.dof_points[vert]
     q = 0.5 * np.einsum("ij,jk,ik->i", xv, A, xv) + xv @ c
     dlt = p[vert] - q
-    assert np.std(dlt) <= 1e-6 * np.std(q)
+    print(f"[gpu fullsize] {name} patch test: std(p - q) / std(q) = {np.std(dlt) / np.std(q):.2e}")
+    assert np.std(dlt) <= _PATCH_BAR[name] * np.std(q)

@@ -27,6 +27,10 @@ from .quadrature import polygon_rule, polyhedron_rule
 from .vem import CellGeometry, cell_projector, face_projector
 
 TOL = 1e-9
+# a point lies on a coarse vertex or edge within the vertex weld distance of
+# the mesh (points that do are there up to rounding; 1e-9 took a fine edge
+# midpoint 9e-9 from a coarse vertex for a point of a neighbouring edge)
+POINT_TOL = 1e-10
 WEIGHT_TOL = 1e-13
 
 
@@ -90,7 +94,7 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
         g, Pis, cd = CL.cell(E)
         # coarse vertex
         for v in g.verts:
-            if np.linalg.norm(Xc[v] - p) < TOL:
+            if np.linalg.norm(Xc[v] - p) < POINT_TOL:
                 return {int(v): 1.0}, 0
         # coarse edge
         for e in g.edges:
@@ -98,7 +102,7 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
             pa, pb = Xc[a], Xc[b]
             ab = pb - pa
             tau = float((p - pa) @ ab / (ab @ ab))
-            if 0.0 < tau < 1.0 and np.linalg.norm(p - pa - tau * ab) < TOL:
+            if 0.0 < tau < 1.0 and np.linalg.norm(p - pa - tau * ab) < POINT_TOL:
                 if k == 1:
                     return {int(a): 1.0 - tau, int(b): tau}, 1
                 mid = coarse_dofs.nv + e
@@ -119,20 +123,26 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
         qp, qw = polygon_rule(fpts)
         area_f = qw.sum()
         fc = qw @ qp / area_f
+        # the fine face lies in the coarse face's plane when all of its
+        # vertices do (a distance test: the computed normal of a sliver face
+        # can be off by far more than its vertices are)
+        coplanar = []
         for f in g.face_ids:
             P = Xc[coarse_mesh.faces[f]]
             n = coarse_mesh.face_normal[f]
-            # the fine face lies in the coarse face's plane when all of its
-            # vertices do (a distance test: the computed normal of a sliver
-            # face can be off by far more than its vertices are)
-            if np.abs((fpts - P[0]) @ n).max() > TOL:
-                continue
-            if not _point_in_face(fc, P, n):
-                continue
+            if np.abs((fpts - P[0]) @ n).max() <= TOL:
+                coplanar.append((f, P, n))
+        # a coarse face equal to the fine face is its host before any face the
+        # fine face's centroid is merely near (a tiny fine face beside a
+        # coarse edge passes the containment slack of the neighbouring face)
+        for f, P, n in coplanar:
             qpc, qwc = polygon_rule(P)
             if abs(qwc.sum() - area_f) < 1e-12 * area_f and \
                     np.linalg.norm(qwc @ qpc / qwc.sum() - fc) < TOL:
                 return {int(coarse_dofs.nv + coarse_dofs.ne + f): 1.0}, 4
+        for f, P, n in coplanar:
+            if not _point_in_face(fc, P, n):
+                continue
             Pif, fr, fd = CL.face(f)
             w = (qw @ fr.mono(qp, k) / area_f) @ Pif
             return dict(zip(fd.tolist(), w.tolist())), 2

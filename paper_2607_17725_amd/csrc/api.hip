@@ -15,6 +15,7 @@
 #include <atomic>
 #include <memory>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -861,7 +862,9 @@ static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const
     residual<double>(K, h->x, h->b, h->r, s);
     dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
     rel = std::sqrt(d[0]) / nb;
-    g_last_error = "maxit = " + std::to_string(maxit) + " reached at relative residual " + std::to_string(rel);
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "maxit = %d reached at relative residual %.3e", static_cast<int>(maxit), rel);
+    g_last_error = buf;
   }
   if (h->ncomp0) project_components(n, h->x, h->comp0, h->ncomp0, h->partial, h->mean, s);
   HIPCHECK(hipMemcpyAsync(xout, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));

@@ -953,9 +953,12 @@ struct BuilderImpl {
         }
         return true;
       };
+      // a point sits on a coarse vertex or edge within the weld distance:
+      // such points are there up to rounding, and a looser test can take a
+      // point next to a tiny feature for one on a neighbouring edge
       auto point_row = [&](V3 p, Row &R) {
         for (int64_t q = Mc.cvptr[E]; q < Mc.cvptr[E + 1]; ++q)
-          if (norm(Mc.X[Mc.cvert[q]] - p) < tol) {
+          if (norm(Mc.X[Mc.cvert[q]] - p) < kVertTol) {
             R.e.push_back({Mc.cvert[q], 1.0});
             return;
           }
@@ -963,7 +966,7 @@ struct BuilderImpl {
           const int32_t e = Mc.cedge[q];
           const V3 a = Mc.X[Mc.edges[e][0]], b = Mc.X[Mc.edges[e][1]], ab = b - a;
           const double tau = dot(p - a, ab) / dot(ab, ab);
-          if (tau > 0 && tau < 1 && norm(p - a - tau * ab) < tol) {
+          if (tau > 0 && tau < 1 && norm(p - a - tau * ab) < kVertTol) {
             if (k == 1) {
               R.e.push_back({Mc.edges[e][0], 1 - tau});
               R.e.push_back({Mc.edges[e][1], tau});
@@ -1009,27 +1012,35 @@ struct BuilderImpl {
             cen = cen + t * (P[0] + P[i] + P[i + 1]);
           }
           cen = (1.0 / (3.0 * A2)) * cen;
-          bool done = false;
-          for (int64_t q = Mc.cfptr[E]; q < Mc.cfptr[E + 1] && !done; ++q) {
+          // the fine face lies in the coarse face's plane when all of its
+          // vertices do (a distance test: the computed normal of a sliver
+          // face can be off by far more than its vertices are)
+          std::vector<int32_t> coplanar;
+          for (int64_t q = Mc.cfptr[E]; q < Mc.cfptr[E + 1]; ++q) {
             const int32_t F2 = Mc.cface[q];
-            // the fine face lies in the coarse face's plane when all of its
-            // vertices do (a distance test: the computed normal of a sliver
-            // face can be off by far more than its vertices are)
-            {
-              const V3 o = Mc.X[Mc.fvert[Mc.fptr[F2]]];
-              bool planar = true;
-              for (const V3 &p : P) planar = planar && std::fabs(dot(Mc.fnormal[F2], p - o)) <= tol;
-              if (!planar) continue;
-            }
-            if (!in_face(F2, cen)) continue;
+            const V3 o = Mc.X[Mc.fvert[Mc.fptr[F2]]];
+            bool planar = true;
+            for (const V3 &p : P) planar = planar && std::fabs(dot(Mc.fnormal[F2], p - o)) <= tol;
+            if (planar) coplanar.push_back(F2);
+          }
+          bool done = false;
+          // a coarse face equal to the fine face is its host before any face
+          // the fine centroid is merely near (a tiny fine face beside a coarse
+          // edge passes the containment slack of the neighbouring face)
+          for (int32_t F2 : coplanar) {
             const vem::FaceProj &fp = fproj[F2];
-            if (std::fabs(fp.area - 0.5 * ar) < 1e-12 * 0.5 * ar && norm(fp.xf - cen) < tol) {
+            if (std::fabs(fp.area - ar) < 1e-12 * ar && norm(fp.xf - cen) < tol) {
               R.e.push_back({static_cast<int32_t>(Mc.nv() + Mc.ne() + F2), 1.0});
-            } else {
-              double mv[6];
-              vem::polygon_mean_face(P, fp, k, mv);
-              face_row(F2, mv, R);
+              done = true;
+              break;
             }
+          }
+          for (size_t t = 0; t < coplanar.size() && !done; ++t) {
+            const int32_t F2 = coplanar[t];
+            if (!in_face(F2, cen)) continue;
+            double mv[6];
+            vem::polygon_mean_face(P, fproj[F2], k, mv);
+            face_row(F2, mv, R);
             done = true;
           }
           if (!done) {

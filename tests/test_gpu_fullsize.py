@@ -24,9 +24,10 @@ torch = pytest.importorskip("torch")
 # constants to ~1e-9 of their row sums (measured on the host from the
 # element blocks), the plates' to ~1e-11; a missing contribution shows at O(1)
 _CONST_BAR = {"c3": 1e-9, "c4": 1e-7}
-# patch test: the sheet's pressure solve is far worse conditioned, so its
-# 1e-10 residual leaves a larger pressure error
-_PATCH_BAR = {"c3": 1e-6, "c4": 1e-4}
+# patch-test tolerance: the mixed solver's residual floor on the sheet sits
+# near 4e-10, so the sheet solves to its workload's own 1e-8 (the pressure
+# error there measured 1.7e-10 of std(q))
+_PATCH_TOL = {"c3": 1e-10, "c4": 1e-8}
 
 
 @pytest.fixture(scope="module", params=["c3", "c4"])
@@ -103,7 +104,7 @@ def test_patch_test_solve(grid128):
     c = rng.standard_normal(3)
     X = g.vertices
     u = (X @ A + c[None, :]).ravel()                   # grad of q = 0.5 x^T A x + c.x
-    p, st = h.solve(_dev(u), tol=1e-10, precision=1, maxit=2000)
+    p, st = h.solve(_dev(u), tol=_PATCH_TOL[name], precision=1, maxit=2000)
     print(f"[gpu fullsize] {name} patch test: {st['iterations']} iterations, residual {st['rel_residual']:.2e}")
     p = p.cpu().numpy()
     vert = g.dof_kind == 0
@@ -111,4 +112,4 @@ def test_patch_test_solve(grid128):
     q = 0.5 * np.einsum("ij,jk,ik->i", xv, A, xv) + xv @ c
     dlt = p[vert] - q
     print(f"[gpu fullsize] {name} patch test: std(p - q) / std(q) = {np.std(dlt) / np.std(q):.2e}")
-    assert np.std(dlt) <= _PATCH_BAR[name] * np.std(q)
+    assert np.std(dlt) <= 1e-6 * np.std(q)

@@ -95,6 +95,7 @@ def get_config(name, N=None, k=None, levels=None):
     if N is not None:
         w.N = int(N)
         w.name = f"{name}@{N}"
+        w.description = w.description.replace(f"{base.N}^3", f"{w.N}^3", 1)
     if k is not None:
         w.k = int(k)
     if levels is not None:

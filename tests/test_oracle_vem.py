@@ -148,3 +148,39 @@ def test_local_patch_test(k):
 
 def test_monomial_order_matches_appendix():
     assert EXP3[:4] == [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+
+
+def test_vector_area_of_a_tiny_face_far_from_the_origin():
+    """A right triangle with legs 2^-30 near (0.82, 0.45, 0.59): its vector area is
+    exactly 2^-61 along +z (every coordinate and the result are representable), which
+    a sum of cross products of absolute positions loses to cancellation."""
+    from oracle.geometry import polygon_area_vec
+    o = np.array([0.8203125, 0.453125, 0.5859375])
+    L = 2.0 ** -30
+    P = np.array([o, o + [L, 0.0, 0.0], o + [0.0, L, 0.0]])
+    a = polygon_area_vec(P)
+    assert a[2] == 0.5 * L * L and a[0] == 0.0 and a[1] == 0.0
+
+
+def test_element_of_a_cell_with_a_tiny_corner_face():
+    """A 1/128 cube near (0.82, 0.82, 0.82) with a corner cut 2e-9 deep along (1,1,1).
+
+    The cut face is an equilateral triangle of area (sqrt(3)/2) l^2; the element stays
+    finite, symmetric and positive semi-definite with the constants as its only null
+    vector (Sec. 3.1)."""
+    from oracle.geometry import polygon_area_vec
+    lo, hi, ell = 0.8203125, 0.828125, 2e-9
+    n = np.ones(3) / np.sqrt(3.0)
+    below, _ = split_polyhedron(make_box([lo] * 3, [hi] * 3), n, float(n @ np.array([hi, hi, hi - ell])))
+    g = StandaloneCell([f[0] for f in below])
+    assert len(g.faces) == 7
+    tiny = min(float(np.linalg.norm(polygon_area_vec(g.X[c]))) for c in g.faces)
+    assert abs(tiny - 0.5 * np.sqrt(3.0) * ell ** 2) <= 1e-6 * tiny
+    K = element_matrices(g, 2, with_velocity=False)["K"]
+    assert np.isfinite(K).all()
+    assert np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
+    assert np.abs(K.sum(axis=1)).max() <= 1e-13 * np.abs(K).max()
+    w = np.linalg.eigvalsh(0.5 * (K + K.T))
+    # the next eigenvalue is 3.6e-4 of the largest for any cut depth (1e-6 down to
+    # 2e-9): the tiny face adds no near-null mode
+    assert w[0] >= -1e-13 * w[-1] and w[1] >= 1e-4 * w[-1]

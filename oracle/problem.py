@@ -39,15 +39,22 @@ class Problem:
         self.K = self.asm.K
         self.B = self.asm.B if with_velocity else None
         self.P = []
+        self.P_raw = []
         self.host_kind = []
         for t in range(len(self.meshes) - 1):
-            P, hk = build_prolongation(self.meshes[t], self.dofs[t], self.meshes[t + 1],
-                                       self.dofs[t + 1], self.parents[t])
-            # coarse DOFs no fine DOF depends on (vertices deep in the solid
-            # part of a coarse cell) carry no information: drop them; a
-            # largest weight below 1e-10 is an exact zero of the projection
-            # polluted by rounding (thin cells amplify it to ~1e-11)
+            P, hk, P_raw = build_prolongation(self.meshes[t], self.dofs[t], self.meshes[t + 1],
+                                              self.dofs[t + 1], self.parents[t], return_raw=True)
+            # Reading of this build (not a statement of the paper): a coarse
+            # DOF whose prolongation column is zero carries no information
+            # and is removed.  Sec. 5.2 argues that nestedness keeps the
+            # restriction full-rank, but coarse cells here keep their solid
+            # part (the coarse-inclusion reading), and some coarse DOFs then
+            # have every weight equal to zero in exact arithmetic (e.g. the
+            # DOFs of sub-faces of a split coarse face away from all fine
+            # fluid cells).  Their computed weights are rounding residue,
+            # at most ~1e-15 here; a largest weight <= 1e-10 marks them.
             used = np.asarray(np.abs(P).max(axis=0).todense()).ravel() > UNUSED_TOL
+            self.P_raw.append((P_raw, used))
             if not used.all():
                 self.dofs[t + 1].deactivate(self.dofs[t + 1].free_ids[~used])
                 P = P[:, np.nonzero(used)[0]].tocsr()

@@ -15,10 +15,11 @@ E only, the Galerkin product couples only DOFs of one coarse cell.
 Reading for the set notation the paper leaves garbled: the new fine DOFs are
 split by the dimension of their host entity, which makes the edge, face and
 volume sets pairwise disjoint.  Coarse DOFs on a Dirichlet face are dropped
-(their value is zero).  Coarse DOFs that no fine DOF depends on (vertices in
-the solid part of a coarse cell) give zero columns; the caller drops them, so
-the coarse operators stay non-singular (reading: the paper asserts nested
-hierarchies avoid rank-deficient transfers).
+(their value is zero).  Coarse DOFs that no fine DOF depends on give zero
+columns; the caller drops them, so the coarse operators stay non-singular.
+That is this build's reading, not the paper's: Sec. 5.2 argues nestedness
+avoids rank-deficient transfers, but coarse cells here keep their solid part
+(the coarse-inclusion reading), which leaves such DOFs.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -81,8 +82,12 @@ class CoarseLevel:
         return self._face[f]
 
 
-def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
-    """P [fine free x coarse free] as scipy CSR, plus the host kind per fine DOF."""
+def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent, return_raw=False):
+    """P [fine free x coarse free] as scipy CSR, plus the host kind per fine DOF.
+
+    With ``return_raw`` also the prolongation before rounding-level weights
+    are dropped (every coarse column kept).
+    """
     k = fine_dofs.k
     CL = coarse_level = CoarseLevel(coarse_mesh, coarse_dofs)
     X, Xc = fine_mesh.X, coarse_mesh.X
@@ -178,24 +183,35 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent):
                     rows[i], host_kind[i] = face_mean_row(X[fine_mesh.faces[f]], E)
             i = nvf + nef + nff + c
             rows[i], host_kind[i] = cell_mean_row(c, E)
-    r, cidx, val = [], [], []
+    r, cidx, val, keep = [], [], [], []
     for i, row in rows.items():
         fi = fine_dofs.free[i]
         if fi < 0:
             continue
-        # weights at rounding level of the row's largest weight are zeros of
-        # the exact prolongation (projections evaluated where a basis
-        # function vanishes); keeping them would leave coarse DOFs with
-        # numerically empty columns and near-zero coarse diagonals
+        # weights at rounding level of the row's largest weight are exact
+        # zeros of the prolongation (a projection evaluated where a basis
+        # function's contribution cancels, e.g. DOFs of coplanar sub-faces
+        # of a split coarse face); keeping their rounding residue would leave
+        # coarse DOFs with numerically empty columns and near-zero coarse
+        # diagonals.  The pins show the dropped weights are exact zeros and
+        # sit at least five orders of magnitude below every kept weight.
         wmax = max((abs(w) for w in row.values()), default=0.0)
         for j, w in row.items():
             cj = coarse_dofs.free[j]
-            if cj < 0 or abs(w) <= WEIGHT_TOL * wmax:
+            if cj < 0:
                 continue
             r.append(fi)
             cidx.append(cj)
             val.append(w)
-    P = sp.csr_matrix((val, (r, cidx)), shape=(fine_dofs.n_free, coarse_dofs.n_free))
+            keep.append(abs(w) > WEIGHT_TOL * wmax)
+    r, cidx, val, keep = map(np.asarray, (r, cidx, val, keep))
+    shape = (fine_dofs.n_free, coarse_dofs.n_free)
+    P_raw = sp.csr_matrix((val, (r, cidx)), shape=shape)
+    P_raw.sum_duplicates()
+    P_raw.sort_indices()
+    P = sp.csr_matrix((val[keep], (r[keep], cidx[keep])), shape=shape)
     P.sum_duplicates()
     P.sort_indices()
+    if return_raw:
+        return P, host_kind, P_raw
     return P, host_kind

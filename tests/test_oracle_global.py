@@ -141,16 +141,18 @@ def test_prolongation_reproduces_polynomials(fx, request):
     pb = request.getfixturevalue(fx)
     q, _ = _poly(pb.k, 5)
     if pb.w.dirichlet_top:
-        # polynomials vanishing on z = 1
-        q0 = q
-        q = lambda X: (1.0 - np.atleast_2d(X)[:, 2]) * q0(X)
+        # polynomials of order k vanishing on z = 1
         if pb.k == 1:
-            pytest.skip("a degree-2 product is not reproduced at order 1")
+            q = lambda X: 0.7 * (1.0 - np.atleast_2d(X)[:, 2])
+        else:
+            q1, _ = _poly(1, 5)
+            q = lambda X: (1.0 - np.atleast_2d(X)[:, 2]) * q1(X)
     for t, P in enumerate(pb.P):
         Dc = _dof_values(pb, t + 1, q)
         Df = _dof_values(pb, t, q)
-        # coarse DOFs whose largest weight is below 1e-10 are dropped as unused
-        assert np.abs(P @ Dc - Df).max() < 1e-9 * max(np.abs(Df).max(), 1.0)
+        # measured: 6e-16 (c1), 7e-15 (c3), 4e-13 (c4, whose 1e-5-thin cells
+        # amplify rounding in their local projections)
+        assert np.abs(P @ Dc - Df).max() < 1e-11 * max(np.abs(Df).max(), 1.0)
 
 
 def test_prolongation_trilinear_on_uncut_grid():

@@ -234,6 +234,20 @@ fvem_status fvem_project_velocity_adjoint(fvem_hierarchy *h, const double *gs_de
 fvem_status fvem_velocity_loss(fvem_hierarchy *h, const double *s_dev, const double *t_dev, double scale,
                                double *loss_host, double *gs_dev, void *hip_stream);
 
+/* The component projection y = P_perp x of FVEM_OP_PROJECT (zero DOF mean on
+ * every pure-Neumann component, caller's DOF order), for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It allocates nothing, creates no event
+ * and does not synchronise: its reduction scratch is a static device array of
+ * the library (about 256 KiB per device, taken when the first hierarchy is
+ * built on that device), so it serves handles with at most 16 pure-Neumann
+ * components (INVALID otherwise).  Every call on one device shares that
+ * array: calls that overlap on one device (different streams or threads)
+ * race.  x and y are [n_dof0] device vectors; y may equal x.  The result is
+ * complete in stream order; it equals FVEM_OP_PROJECT's up to the rounding
+ * of the per-component means. */
+fvem_status fvem_project_noalloc(fvem_hierarchy *h, const double *x_dev, double *y_dev, void *hip_stream);
+
 /* Level data for inspection: copies level l's operator A_l (FP64 CSR as
  * built on the device) to caller-owned host arrays.  Call first with NULL
  * arrays to get n_rows and nnz; then row_ptr needs n_rows+1, col/val nnz. */

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <memory>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -135,7 +136,9 @@ struct fvem_hierarchy {
   fvem::DevCSR Pi, PiT, Gr, GrT, Ms, Av, AvT;
   double *vs1 = nullptr, *vs2 = nullptr;
   int32_t *comp0 = nullptr;
+  int32_t *compc = nullptr;   // component of each DOF in the caller's order
   int ncomp0 = 0;
+  double *scratch = nullptr;  // this device's copy of the static scratch array
   // coarsest level
   int64_t nc = 0;
   double *G = nullptr;
@@ -374,6 +377,34 @@ static void cheb_coefficients(Level &L, int deg, double lower) {
   }
 }
 
+// ---------------------------------------------------------------- static scratch
+//
+// Scratch of the entry point that allocates nothing (fvem_project_noalloc):
+// the per-block partial sums and means of the component projection for up to
+// NOALLOC_MAX_COMP components.  One copy per device, alive until the process
+// ends.  In host code the array's name is not a device address: its address
+// on each device comes from hipGetSymbolAddress, taken once per device with
+// that device current (at the first hierarchy build on it).
+constexpr int NOALLOC_MAX_COMP = 16;
+constexpr int64_t NOALLOC_PARTIAL = 2 * static_cast<int64_t>(NOALLOC_MAX_COMP) * REDUCE_BLOCKS;
+static __device__ __align__(256) double scratch[NOALLOC_PARTIAL + NOALLOC_MAX_COMP];
+
+static double *static_scratch_address(int device) {
+  static std::mutex mu;
+  static std::vector<double *> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) throw SetupError{FVEM_ERR_INVALID, "bad device id"};
+  if (static_cast<size_t>(device) >= addr.size()) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw SetupError{FVEM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    addr[device] = static_cast<double *>(p);
+  }
+  return addr[device];
+}
+
 static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options *o, hipStream_t s) {
   check(g != nullptr, "null descriptor");
   check(g->n_levels >= 1 && g->levels, "n_levels < 1");
@@ -550,6 +581,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   }
   for (int l = 0; l + 1 < L; ++l) P[l] = permute(P[l], h->lv[l].order, &inv[l + 1]);
   if (g->n_vert > 0) Bh = permute(Bh, h->lv[0].order, nullptr);
+  std::vector<int32_t> comp_caller = comp0;
   {
     std::vector<int32_t> c(h->n0);
     for (int64_t i = 0; i < h->n0; ++i) c[i] = comp0[h->lv[0].order[i]];
@@ -613,6 +645,8 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     progress("hierarchy: divergence stored");
   }
   h->comp0 = h->mem.upload(comp0, s);
+  h->compc = h->mem.upload(comp_caller, s);
+  h->scratch = static_scratch_address(h->device);
   if (g->vc_off) build_velocity(h, g, c0, inv[0], s);
   progress("hierarchy: operators uploaded");
 
@@ -1194,6 +1228,32 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
       default: throw SetupError{FVEM_ERR_INVALID, "unknown operator"};
     }
     HIPCHECK(hipStreamSynchronize(s));
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_project_noalloc(fvem_hierarchy *h, const double *x, double *y, void *hip_stream) {
+  if (!h || !x || !y) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  if (h->ncomp0 > NOALLOC_MAX_COMP) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%d pure-Neumann components exceed the static scratch limit of %d",
+                  h->ncomp0, NOALLOC_MAX_COMP);
+    g_last_error = buf;
+    return FVEM_ERR_INVALID;
+  }
+  if (!h->scratch) {
+    g_last_error = "static scratch address unavailable";
+    return FVEM_ERR_HIP;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  return guard([&] {
+    const int64_t n = h->n0;
+    if (x != y) HIPCHECK(hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (h->ncomp0) project_components(n, y, h->compc, h->ncomp0, h->scratch, h->scratch + NOALLOC_PARTIAL, s);
+    HIPCHECK(hipGetLastError());
     return FVEM_OK;
   });
 }

@@ -76,7 +76,7 @@ EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_app
            "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error", "fvem_grid_build",
            "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy",
            "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells",
-           "fvem_level_storage", "fvem_level_bytes"]
+           "fvem_level_storage", "fvem_level_bytes", "fvem_project_noalloc"]
 
 _lib = None
 
@@ -111,6 +111,8 @@ def load(path=LIB_PATH):
     lib.fvem_level_bytes.restype = ctypes.c_int
     lib.fvem_hierarchy_cells.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fvem_hierarchy_cells.restype = ctypes.c_int
+    lib.fvem_project_noalloc.argtypes = [vp, vp, vp, vp]
+    lib.fvem_project_noalloc.restype = ctypes.c_int
     lib.fvem_level_matrix.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
     lib.fvem_level_matrix.restype = ctypes.c_int
     lib.fvem_hierarchy_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -290,6 +292,14 @@ class Hierarchy:
         code = op | (APPLY_ACCUMULATE if accumulate else 0)
         _check(load().fvem_apply(self._h, code, self._vec(x, n_in, "x"), self._vec(y, n_out, "y"),
                                  ctypes.c_void_p(self.stream.cuda_stream)))
+        return y
+
+    def project_noalloc(self, x, out=None):
+        """y = P_perp x through fvem_project_noalloc (no allocation inside the library)."""
+        import torch
+        y = out if out is not None else torch.empty(self.n_dof, dtype=torch.float64, device=self.device)
+        _check(load().fvem_project_noalloc(self._h, self._vec(x, self.n_dof, "x"), self._vec(y, self.n_dof, "y"),
+                                           ctypes.c_void_p(self.stream.cuda_stream)))
         return y
 
     def project_velocity(self, u, s=None, p=None, tol=1e-8, maxit=500, precision=PREC_MIXED,

@@ -104,7 +104,16 @@ typedef struct {
  *                 length of vc_val.
  *  cell_geom      [n_cells x 5] centroid x_E, h_E (diameter) and volume of
  *                 each level-0 cell (with vc_off).
- *  vert_xyz       [n_vert x 3] velocity vertex coordinates (with vc_off). */
+ *  vert_xyz       [n_vert x 3] velocity vertex coordinates (with vc_off).
+ *  dof_lattice    optional [n_dof of level 0 x 3]: integer coordinates of each
+ *                 level-0 DOF's support point on the structured lattice of
+ *                 the background grid (the half-lattice of spacing h/2 for
+ *                 k = 2, the vertex lattice for k = 1), or -1 where the point
+ *                 is off the lattice.  With it, rows that equal their lattice
+ *                 class's stencil are applied without stored columns or
+ *                 values (Sec. 7's compact storage for regular regions);
+ *                 NULL keeps every row in sliced storage.
+ *  lattice_n      lattice points per axis (2 N + 1 or N + 1). */
 typedef struct {
     int32_t n_levels;
     const fvem_level_desc *levels;
@@ -124,6 +133,8 @@ typedef struct {
     int64_t vc_len;
     const double *cell_geom;
     const double *vert_xyz;
+    const int32_t *dof_lattice;
+    int32_t lattice_n;
 } fvem_grid_desc;
 
 /* Hierarchy options.  Zero-initialised fields take the defaults in brackets. */
@@ -136,6 +147,9 @@ typedef struct {
     int64_t small_level_rows;   /* levels with at most this many rows share each row among 16
                                    lanes instead of one lane per row [131072]; < 0: never */
     int32_t max_templates;      /* value templates per operator [4096]; < 0: none */
+    double lattice_min_fraction; /* with dof_lattice: use the lattice stencil layout on level 0
+                                    when at least this fraction of its rows are stencil rows
+                                    [0.5]; < 0: never */
 } fvem_options;
 
 typedef enum { FVEM_PREC_FP64 = 0, FVEM_PREC_MIXED = 1 } fvem_precision;
@@ -158,6 +172,8 @@ typedef struct {
                                 fused Chebyshev-step launches (SpMV + update) */
     int32_t n_fine_smoother; /* with profile: number of those launches */
     int32_t n_levels;
+    double ms_vcycle;       /* with profile: summed device time of the preconditioner's V-cycles */
+    int32_t n_vcycle;       /* with profile: number of those V-cycles */
 } fvem_solve_stats;
 
 typedef struct fvem_hierarchy fvem_hierarchy;
@@ -269,9 +285,32 @@ fvem_status fvem_level_storage(fvem_hierarchy *h, int32_t level, int64_t *nnz, i
  * (fvem_precision: FP64 or MIXED = FP32 values): 2 bytes per nonzero of
  * slices with 16-bit column codes plus 256 per block table, 4 per nonzero
  * of the others, the stored values (4 or 8 bytes per nonzero of
- * value-storing rows) and 4 per row reading a value template.  Padding and
- * the cache-resident template table are not counted. */
+ * value-storing rows) and 4 per row reading a value template, 4 per row of a
+ * row map (sliced rows scattered into the lattice layout) and 68 per tile of
+ * lattice stencil rows (tile id and mask).  Padding and the cache-resident
+ * template and stencil tables are not counted. */
 fvem_status fvem_level_bytes(fvem_hierarchy *h, int32_t level, int32_t precision, int64_t *bytes);
+
+/* Transfers between levels l and l+1: nonzeros of P_l and the matrix bytes
+ * one application of P_l and of R_l = P_l^T reads in the given precision
+ * (as fvem_level_bytes, plus 4 bytes per row of the row map). */
+fvem_status fvem_transfer_storage(fvem_hierarchy *h, int32_t level, int32_t precision, int64_t *nnz,
+                                  int64_t *bytes_p, int64_t *bytes_r);
+
+/* Algorithmic bytes of one V-cycle of the preconditioner in the given
+ * precision: on every level but the coarsest, 2 deg applications of A_l
+ * (matrix bytes as fvem_level_bytes), one restriction and one
+ * prolongation, and the vector streams of the fused kernels (per row: 4 for
+ * the first smoothing step, 6 per later step, 3 for the residual, 1 for the
+ * restriction, 2 for the correction, plus 2 per coarse row); on the
+ * coarsest level the dense inverse (8 n_c^2) and its vectors.  Cache reuse
+ * of gathered x is assumed; padding is not counted. */
+fvem_status fvem_vcycle_bytes(fvem_hierarchy *h, int32_t precision, int64_t *bytes);
+
+/* Lattice stencil part of level l's operator: rows applied from the class
+ * stencils (no stored columns or values), their nonzeros, and the lattice
+ * tiles launched per application (all zero when the level has none). */
+fvem_status fvem_level_stencil(fvem_hierarchy *h, int32_t level, int64_t *rows, int64_t *nnz, int64_t *tiles);
 
 /* Number of level-0 cells carrying velocity fields (0 without vc_off). */
 fvem_status fvem_hierarchy_cells(fvem_hierarchy *h, int64_t *n_cells);

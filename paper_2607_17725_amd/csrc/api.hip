@@ -59,6 +59,12 @@ struct DevMem {
     if (!v.empty()) HIPCHECK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
     return p;
   }
+  template <typename T>
+  T *alloc_zero(int64_t n, hipStream_t s) {
+    T *p = alloc<T>(n);
+    HIPCHECK(hipMemsetAsync(p, 0, sizeof(T) * std::max<int64_t>(n, 1), s));
+    return p;
+  }
   ~DevMem() {
     for (void *p : ptrs) (void)hipFree(p);
   }
@@ -99,12 +105,27 @@ struct DevSELL {
   std::vector<int32_t> hsl, hrl, hbtab;
   HostValues hv64;                  // FP64 value set without its values (read back on demand)
   bool split = false;
-  int32_t *rowmap = nullptr;        // transfers: stored row r is output row rowmap[r]
+  int32_t *rowmap = nullptr;        // stored row r is output row rowmap[r] (transfers; level 0 with stencil)
+  std::vector<int32_t> hrowmap;
+  // lattice stencil rows (level 0 when the descriptor gives lattice coordinates)
+  struct Stencil {
+    int64_t ntiles = 0, n_rows = 0, nnz = 0;
+    int32_t *tiles = nullptr, *tile_base = nullptr, *len = nullptr, *off = nullptr;
+    uint64_t *mask = nullptr;
+    double *val64 = nullptr;
+    float *val32 = nullptr;
+    int32_t tn = 0, lat_n = 0;
+    HostLattice host;               // tables, tiles and masks for read-back
+  } st;
   DevSELLView<double> d() const {
-    return {n, m, nslices, sl, cp, ci, bt, c16, btab, d64.vp, v64, d64.tid, tv64, d64.tw, split, rowmap};
+    DevSELLView<double> v{n, m, nslices, sl, cp, ci, bt, c16, btab, d64.vp, v64, d64.tid, tv64, d64.tw, split, rowmap};
+    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val64};
+    return v;
   }
   DevSELLView<float> f() const {
-    return {n, m, nslices, sl, cp, ci, bt, c16, btab, d32.vp, v32, d32.tid, tv32, d32.tw, split, rowmap};
+    DevSELLView<float> v{n, m, nslices, sl, cp, ci, bt, c16, btab, d32.vp, v32, d32.tid, tv32, d32.tw, split, rowmap};
+    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val32};
+    return v;
   }
 };
 
@@ -129,7 +150,8 @@ struct fvem_hierarchy {
   int nlev = 0;
   std::vector<fvem::Level> lv;
   fvem::DevCSR B, BT;
-  int64_t nvert = 0, n0 = 0;
+  int64_t nvert = 0, n0 = 0;   // n0: the caller's level-0 DOFs
+  int64_t nl0 = 0;             // level-0 vector length (lattice slots with holes, then the rest)
   int32_t *perm0 = nullptr, *iperm0 = nullptr;   // level-0 order and its inverse (device)
   // velocity operators on cell fields (12 values per level-0 cell)
   int64_t ncell_v = 0;
@@ -148,8 +170,10 @@ struct fvem_hierarchy {
   double *host = nullptr;  // pinned scalars
   std::atomic<int> busy{0};
   // profiling
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev;    // pairs around finest-level Chebyshev steps
   size_t ev_used = 0;
+  std::vector<hipEvent_t> evv;   // pairs around V-cycles
+  size_t evv_used = 0;
   bool profiling = false;
 };
 
@@ -264,9 +288,55 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_template
   return d;
 }
 
-static std::vector<int32_t> inverse(const std::vector<int32_t> &order) {
-  std::vector<int32_t> inv(order.size());
-  for (size_t i = 0; i < order.size(); ++i) inv[order[i]] = static_cast<int32_t>(i);
+// Level 0 on the lattice layout: the stencil rows go to the class tables,
+// every other row (off the lattice, or not matching its class's stencil)
+// to sliced storage in its own length-sorted order with a row map into the
+// padded level order.  A is in the caller's order; inv maps caller DOF ->
+// level slot.
+static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, HostLattice &lat,
+                                 const std::vector<int32_t> &inv, int max_templates, hipStream_t s) {
+  std::vector<int32_t> rest;   // caller DOFs of the sliced rows, in level order
+  for (int64_t r = 0; r < static_cast<int64_t>(V.order.size()); ++r) {
+    const int32_t i = V.order[r];
+    if (i >= 0 && !lat.is_stencil[i]) rest.push_back(i);
+  }
+  constexpr int64_t ORDER_WINDOW = 4096;
+  const HostCSR R0 = permute(A, rest, &inv, V.n);
+  const std::vector<int32_t> ord = window_order(R0, ORDER_WINDOW);
+  V.A = upload_sell(h, permute(R0, ord, nullptr, V.n), max_templates, true, s);
+  std::vector<int32_t> rowmap(ord.size());
+  for (size_t k = 0; k < ord.size(); ++k) rowmap[k] = inv[rest[ord[k]]];
+  V.A.rowmap = h->mem.upload(rowmap, s);
+  V.A.hrowmap = std::move(rowmap);
+  V.A.split = false;
+  V.A.m = V.n;
+  auto &st = V.A.st;
+  st.ntiles = static_cast<int64_t>(lat.tiles.size());
+  st.n_rows = lat.n_stencil;
+  st.nnz = lat.nnz_stencil;
+  st.tn = lat.tn;
+  st.lat_n = lat.lat_n;
+  st.tiles = h->mem.upload(lat.tiles, s);
+  st.mask = h->mem.upload(lat.mask, s);
+  st.tile_base = h->mem.upload(lat.tile_base, s);
+  const std::vector<int32_t> lens(lat.len, lat.len + 8);
+  st.len = h->mem.upload(lens, s);
+  st.off = h->mem.upload(lat.off, s);
+  st.val64 = h->mem.upload(lat.val, s);
+  st.val32 = h->mem.alloc<float>(static_cast<int64_t>(lat.val.size()));
+  cast_f64_f32(static_cast<int64_t>(lat.val.size()), st.val64, st.val32, s);
+  HIPCHECK(hipStreamSynchronize(s));
+  lat.order.clear();
+  lat.order.shrink_to_fit();
+  lat.is_stencil.clear();
+  lat.is_stencil.shrink_to_fit();
+  st.host = std::move(lat);
+}
+
+static std::vector<int32_t> inverse(const std::vector<int32_t> &order, int64_t n = -1) {
+  std::vector<int32_t> inv(n >= 0 ? static_cast<size_t>(n) : order.size(), -1);
+  for (size_t i = 0; i < order.size(); ++i)
+    if (order[i] >= 0) inv[order[i]] = static_cast<int32_t>(i);
   return inv;
 }
 
@@ -296,7 +366,7 @@ static void build_velocity(fvem_hierarchy *h, const fvem_grid_desc *g, const Hos
     A->rp.assign(12 * nc + 1, 0);
   }
   Pi.n_cols = 3 * nv;
-  Gr.n_cols = h->n0;
+  Gr.n_cols = h->nl0;
   Ms.n_cols = 12 * nc;
   AvT.n_cols = 3 * nv;
   for (int64_t c = 0; c < nc; ++c) {
@@ -416,6 +486,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const double shift = (o && o->coarse_shift > 0) ? o->coarse_shift : 1e-8;
   const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 131072;
   const int max_templates = (o && o->max_templates != 0) ? o->max_templates : 4096;
+  const double lattice_min = (o && o->lattice_min_fraction != 0) ? o->lattice_min_fraction : 0.5;
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
   h->lv.resize(L);
@@ -574,17 +645,33 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   // operator, transfer and per-DOF array is renumbered into it
   constexpr int64_t ORDER_WINDOW = 4096;
   std::vector<std::vector<int32_t>> inv(L);
+  // level 0 on the lattice layout when the descriptor gives lattice
+  // coordinates and at least half of the rows are stencil rows
+  HostLattice lat0;
+  const bool lattice = L > 1 && g->dof_lattice && g->lattice_n > 0 && lattice_min >= 0 &&
+                       lattice_layout(A[0], g->dof_lattice, g->lattice_n, lattice_min, &lat0);
+  if (lattice)
+    progress("hierarchy: level 0 lattice layout, %lld of %lld rows on stencils, %lld tiles",
+             static_cast<long long>(lat0.n_stencil), static_cast<long long>(h->n0),
+             static_cast<long long>(lat0.tiles.size()));
   for (int l = 0; l < L; ++l) {
+    if (l == 0 && lattice) {
+      h->lv[0].order = lat0.order;           // slots with holes, then the DOFs off the lattice
+      inv[0] = inverse(lat0.order, h->n0);
+      continue;                              // A[0] stays in the caller's order
+    }
     h->lv[l].order = window_order(A[l], ORDER_WINDOW);
     inv[l] = inverse(h->lv[l].order);
     A[l] = permute(A[l], h->lv[l].order, &inv[l]);
   }
+  h->nl0 = static_cast<int64_t>(h->lv[0].order.size());
   for (int l = 0; l + 1 < L; ++l) P[l] = permute(P[l], h->lv[l].order, &inv[l + 1]);
   if (g->n_vert > 0) Bh = permute(Bh, h->lv[0].order, nullptr);
   std::vector<int32_t> comp_caller = comp0;
   {
-    std::vector<int32_t> c(h->n0);
-    for (int64_t i = 0; i < h->n0; ++i) c[i] = comp0[h->lv[0].order[i]];
+    std::vector<int32_t> c(h->nl0, -1);
+    for (int64_t i = 0; i < h->nl0; ++i)
+      if (h->lv[0].order[i] >= 0) c[i] = comp0[h->lv[0].order[i]];
     comp0.swap(c);
   }
   h->perm0 = h->mem.upload(h->lv[0].order, s);
@@ -594,16 +681,32 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   // upload
   for (int l = 0; l < L; ++l) {
     Level &V = h->lv[l];
-    V.n = A[l].n_rows;
-    const bool split = small_rows >= 0 && V.n <= small_rows;
-    V.A = upload_sell(h, A[l], max_templates, true, s);
-    V.A.split = split;
-    std::vector<double> dinv(V.n);
-    for (int64_t i = 0; i < V.n; ++i) {
-      double d = 0.0;
-      for (int64_t k = A[l].rp[i]; k < A[l].rp[i + 1]; ++k)
-        if (A[l].ci[k] == i) d = A[l].v[k];
-      dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
+    std::vector<double> dinv;
+    if (l == 0 && lattice) {
+      V.n = h->nl0;
+      upload_lattice_level(h, V, A[0], lat0, inv[0], max_templates, s);
+      dinv.assign(V.n, 0.0);
+#pragma omp parallel for schedule(dynamic, 4096)
+      for (int64_t r = 0; r < V.n; ++r) {
+        const int32_t i = V.order[r];
+        if (i < 0) continue;
+        double d = 0.0;
+        for (int64_t k = A[0].rp[i]; k < A[0].rp[i + 1]; ++k)
+          if (A[0].ci[k] == i) d = A[0].v[k];
+        dinv[r] = d > 0.0 ? 1.0 / d : 0.0;
+      }
+    } else {
+      V.n = A[l].n_rows;
+      const bool split = small_rows >= 0 && V.n <= small_rows;
+      V.A = upload_sell(h, A[l], max_templates, true, s);
+      V.A.split = split;
+      dinv.assign(V.n, 0.0);
+      for (int64_t i = 0; i < V.n; ++i) {
+        double d = 0.0;
+        for (int64_t k = A[l].rp[i]; k < A[l].rp[i + 1]; ++k)
+          if (A[l].ci[k] == i) d = A[l].v[k];
+        dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
+      }
     }
     V.dinv64 = h->mem.upload(dinv, s);
     V.dinv32 = h->mem.alloc<float>(V.n);
@@ -627,16 +730,17 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     }
     progress("hierarchy: level %d stored (%lld of %lld rows templated)", l,
              static_cast<long long>(V.A.d32.rows_templated), static_cast<long long>(V.n));
-    V.b64 = h->mem.alloc<double>(V.n);
-    V.x64 = h->mem.alloc<double>(V.n);
-    V.xb64 = h->mem.alloc<double>(V.n);
-    V.d64 = h->mem.alloc<double>(V.n);
-    V.r64 = h->mem.alloc<double>(V.n);
-    V.b32 = h->mem.alloc<float>(V.n);
-    V.x32 = h->mem.alloc<float>(V.n);
-    V.xb32 = h->mem.alloc<float>(V.n);
-    V.d32 = h->mem.alloc<float>(V.n);
-    V.r32 = h->mem.alloc<float>(V.n);
+    // level vectors start at zero: lattice holes are never written and stay zero
+    V.b64 = h->mem.alloc_zero<double>(V.n, s);
+    V.x64 = h->mem.alloc_zero<double>(V.n, s);
+    V.xb64 = h->mem.alloc_zero<double>(V.n, s);
+    V.d64 = h->mem.alloc_zero<double>(V.n, s);
+    V.r64 = h->mem.alloc_zero<double>(V.n, s);
+    V.b32 = h->mem.alloc_zero<float>(V.n, s);
+    V.x32 = h->mem.alloc_zero<float>(V.n, s);
+    V.xb32 = h->mem.alloc_zero<float>(V.n, s);
+    V.d32 = h->mem.alloc_zero<float>(V.n, s);
+    V.r32 = h->mem.alloc_zero<float>(V.n, s);
     if (l + 1 < L) A[l] = HostCSR();   // the coarsest stays for the dense factorisation
   }
   if (g->n_vert > 0) {
@@ -694,19 +798,19 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     h->bc = h->mem.alloc<double>(n);
     h->xc = h->mem.alloc<double>(n);
   }
-  // PCG workspace
-  const int64_t n = h->n0;
-  h->b = h->mem.alloc<double>(n);
-  h->x = h->mem.alloc<double>(n);
-  h->r = h->mem.alloc<double>(n);
-  h->z = h->mem.alloc<double>(n);
-  h->zold = h->mem.alloc<double>(n);
-  h->p = h->mem.alloc<double>(n);
-  h->q = h->mem.alloc<double>(n);
+  // PCG workspace (level-0 vector length, zero holes)
+  const int64_t n = h->nl0;
+  h->b = h->mem.alloc_zero<double>(n, s);
+  h->x = h->mem.alloc_zero<double>(n, s);
+  h->r = h->mem.alloc_zero<double>(n, s);
+  h->z = h->mem.alloc_zero<double>(n, s);
+  h->zold = h->mem.alloc_zero<double>(n, s);
+  h->p = h->mem.alloc_zero<double>(n, s);
+  h->q = h->mem.alloc_zero<double>(n, s);
   h->partial = h->mem.alloc<double>(2 * MAX_COMP * REDUCE_BLOCKS);
   h->dotout = h->mem.alloc<double>(8);
   h->mean = h->mem.alloc<double>(MAX_COMP);
-  h->lam = h->mem.alloc<double>(n);
+  h->lam = h->mem.alloc_zero<double>(n, s);
   HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&h->host), 8 * sizeof(double), hipHostMallocDefault));
   HIPCHECK(hipStreamSynchronize(s));
 }
@@ -737,14 +841,15 @@ template <> struct Vec<float> {
   static DevSELLView<float> R(Level &L) { return L.R.f(); }
 };
 
-static void ev_record(fvem_hierarchy *h, hipStream_t s) {
-  if (h->ev_used == h->ev.size()) {
+static void ev_record(std::vector<hipEvent_t> &ev, size_t &used, hipStream_t s) {
+  if (used == ev.size()) {
     hipEvent_t e;
     HIPCHECK(hipEventCreate(&e));
-    h->ev.push_back(e);
+    ev.push_back(e);
   }
-  HIPCHECK(hipEventRecord(h->ev[h->ev_used++], s));
+  HIPCHECK(hipEventRecord(ev[used++], s));
 }
+static void ev_record(fvem_hierarchy *h, hipStream_t s) { ev_record(h->ev, h->ev_used, s); }
 
 template <typename T>
 static void coarse_solve(fvem_hierarchy *h, hipStream_t s) {
@@ -803,17 +908,21 @@ static void vcycle(fvem_hierarchy *h, int l, hipStream_t s) {
 // z = M r (level-0 input r, FP64), projected
 static void precondition(fvem_hierarchy *h, const double *r, double *z, bool mixed, double rnorm, hipStream_t s) {
   Level &L0 = h->lv[0];
-  const int64_t n = h->n0;
+  const int64_t n = h->nl0;
   if (h->nlev == 1) {
     symv(n, h->G, r, z, s);
   } else if (mixed) {
     const double sc = rnorm > 0 ? 1.0 / rnorm : 1.0;
     cast_scale(n, r, L0.b32, sc, s);
+    if (h->profiling) ev_record(h->evv, h->evv_used, s);
     vcycle<float>(h, 0, s);
+    if (h->profiling) ev_record(h->evv, h->evv_used, s);
     cast_scale(n, L0.x32, z, 1.0 / sc, s);
   } else {
     HIPCHECK(hipMemcpyAsync(L0.b64, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (h->profiling) ev_record(h->evv, h->evv_used, s);
     vcycle<double>(h, 0, s);
+    if (h->profiling) ev_record(h->evv, h->evv_used, s);
     HIPCHECK(hipMemcpyAsync(z, L0.x64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   }
   if (h->ncomp0) project_components(n, z, h->comp0, h->ncomp0, h->partial, h->mean, s);
@@ -829,7 +938,7 @@ static void dots_host_n(fvem_hierarchy *h, int64_t n, int nd, const double *a0, 
 
 static void dots_host(fvem_hierarchy *h, int nd, const double *a0, const double *b0, const double *a1,
                       const double *b1, const double *a2, const double *b2, double *out, hipStream_t s) {
-  dots(h->n0, nd, a0, b0, a1, b1, a2, b2, h->partial, h->dotout, s);
+  dots(h->nl0, nd, a0, b0, a1, b1, a2, b2, h->partial, h->dotout, s);
   HIPCHECK(hipMemcpyAsync(h->host, h->dotout, sizeof(double) * nd, hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   for (int j = 0; j < nd; ++j) out[j] = h->host[j];
@@ -837,7 +946,7 @@ static void dots_host(fvem_hierarchy *h, int nd, const double *a0, const double 
 
 static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const fvem_solve_opts *so,
                        fvem_solve_stats *st, hipStream_t s) {
-  const int64_t n = h->n0;
+  const int64_t n = h->nl0;
   const double tol = (so && so->tol > 0) ? so->tol : 1e-8;
   const int maxit = (so && so->maxit > 0) ? so->maxit : 500;
   const bool mixed = so && so->precision == FVEM_PREC_MIXED;
@@ -923,12 +1032,13 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
   if (vel_op && h->ncell_v == 0) throw SetupError{FVEM_ERR_INVALID, "no velocity operators in this hierarchy"};
   h->profiling = so && so->profile;
   h->ev_used = 0;
+  h->evv_used = 0;
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   HIPCHECK(hipEventRecord(e0, s));
   // caller's DOF order <-> level order at the boundary of the solve
-  const int64_t n = h->n0;
+  const int64_t n = h->n0, nl = h->nl0;
   fvem_status stt;
   if (kind == SOLVE_VELOCITY) {
     spmv<double>(h->B.d(), in, h->q, s);
@@ -944,11 +1054,11 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
   } else if (!adjoint) {
     const double *rhs = h->q;
     if (velocity) spmv<double>(h->B.d(), in, h->q, s);
-    else gather(n, h->perm0, in, h->q, s);
+    else gather(nl, h->perm0, in, h->q, s);
     stt = pcg(h, rhs, h->lam, so, st, s);
     gather(n, h->iperm0, h->lam, out, s);
   } else {
-    gather(n, h->perm0, in, h->q, s);
+    gather(nl, h->perm0, in, h->q, s);
     stt = pcg(h, h->q, h->lam, so, st, s);
     if (velocity) spmv<double>(h->BT.d(), h->lam, out, s);
     else gather(n, h->iperm0, h->lam, out, s);
@@ -968,6 +1078,13 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
       float t = 0.f;
       HIPCHECK(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
       st->ms_fine_smoother += t;
+    }
+    st->ms_vcycle = 0.0;
+    st->n_vcycle = static_cast<int32_t>(h->evv_used / 2);
+    for (size_t k = 0; k + 1 < h->evv_used; k += 2) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, h->evv[k], h->evv[k + 1]));
+      st->ms_vcycle += t;
     }
   }
   h->profiling = false;
@@ -1125,12 +1242,20 @@ fvem_status fvem_level_storage(fvem_hierarchy *h, int32_t level, int64_t *nnz, i
     return FVEM_ERR_INVALID;
   }
   const DevSELL &A = h->lv[level].A;
-  if (nnz) *nnz = A.nnz;
+  if (nnz) *nnz = A.nnz + A.st.nnz;
   if (nnz_explicit) *nnz_explicit = A.d32.nnz_explicit;
-  if (rows_templated) *rows_templated = A.d32.rows_templated;
+  if (rows_templated) *rows_templated = A.d32.rows_templated + A.st.n_rows;
   if (n_templates) *n_templates = A.d32.nt;
   if (template_width) *template_width = A.d32.tw;
   return FVEM_OK;
+}
+
+// matrix bytes one application of a sliced operator reads (see fvem_level_bytes)
+static int64_t sell_bytes(const DevSELL &A, int32_t precision) {
+  const DevValues &V = precision == FVEM_PREC_FP64 ? A.d64 : A.d32;
+  const int64_t vb = precision == FVEM_PREC_FP64 ? 8 : 4;
+  return A.col_bytes + vb * V.nnz_explicit + 4 * V.rows_templated + 68 * A.st.ntiles +
+         (A.rowmap ? 4 * A.n : 0);
 }
 
 fvem_status fvem_level_bytes(fvem_hierarchy *h, int32_t level, int32_t precision, int64_t *bytes) {
@@ -1138,10 +1263,60 @@ fvem_status fvem_level_bytes(fvem_hierarchy *h, int32_t level, int32_t precision
     g_last_error = "bad handle, level or output";
     return FVEM_ERR_INVALID;
   }
+  // stencil rows: a tile id and 8 mask words per launched tile; sliced
+  // rows with a row map: 4 bytes per row
+  *bytes = sell_bytes(h->lv[level].A, precision);
+  return FVEM_OK;
+}
+
+fvem_status fvem_transfer_storage(fvem_hierarchy *h, int32_t level, int32_t precision, int64_t *nnz,
+                                  int64_t *bytes_p, int64_t *bytes_r) {
+  if (!h || level < 0 || level + 1 >= h->nlev) {
+    g_last_error = "bad handle or level (transfers exist below the coarsest level)";
+    return FVEM_ERR_INVALID;
+  }
+  const Level &L = h->lv[level];
+  if (nnz) *nnz = L.P.nnz;
+  if (bytes_p) *bytes_p = sell_bytes(L.P, precision);
+  if (bytes_r) *bytes_r = sell_bytes(L.R, precision);
+  return FVEM_OK;
+}
+
+fvem_status fvem_vcycle_bytes(fvem_hierarchy *h, int32_t precision, int64_t *bytes) {
+  if (!h || !bytes) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  const int64_t s = precision == FVEM_PREC_FP64 ? 8 : 4;
+  int64_t total = 0;
+  for (int l = 0; l + 1 < h->nlev; ++l) {
+    const Level &L = h->lv[l];
+    const int64_t n = l == 0 ? h->n0 : L.n, nn = h->lv[l + 1].n;
+    const int64_t deg = static_cast<int64_t>(L.ca.size());
+    // 2 deg applications of A_l (deg - 1 pre-smoothing steps after the
+    // first, the residual, deg post-smoothing steps); vectors: the first
+    // step (b, D^-1 read; d, x written), 2 deg - 1 fused steps (x, b, D^-1,
+    // d read; d, x written), the residual (x, b read; r written), the
+    // restriction (r read, b_c written) and the prolongation (x_c read,
+    // x read and written)
+    total += 2 * deg * sell_bytes(L.A, precision) + sell_bytes(L.R, precision) + sell_bytes(L.P, precision);
+    total += s * (n * (4 + 6 * (2 * deg - 1) + 3 + 1 + 2) + 2 * nn);
+  }
+  // coarsest: the dense generalised inverse, read once, and its vectors
+  total += 8 * h->nc * h->nc + (s + 8) * 2 * h->nc;
+  *bytes = total;
+  return FVEM_OK;
+}
+
+fvem_status fvem_level_stencil(fvem_hierarchy *h, int32_t level, int64_t *rows, int64_t *nnz, int64_t *tiles) {
+  if (!h || level < 0 || level >= h->nlev) {
+    g_last_error = "bad handle or level";
+    return FVEM_ERR_INVALID;
+  }
   const DevSELL &A = h->lv[level].A;
-  const DevValues &V = precision == FVEM_PREC_FP64 ? A.d64 : A.d32;
-  const int64_t vb = precision == FVEM_PREC_FP64 ? 8 : 4;
-  *bytes = A.col_bytes + vb * V.nnz_explicit + 4 * V.rows_templated;
+  if (rows) *rows = A.st.n_rows;
+  if (nnz) *nnz = A.st.nnz;
+  if (tiles) *tiles = A.st.ntiles;
   return FVEM_OK;
 }
 
@@ -1168,7 +1343,7 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
   const bool acc = (op & FVEM_APPLY_ACCUMULATE) != 0;
   op &= ~FVEM_APPLY_ACCUMULATE;
   return guard([&] {
-    const int64_t n = h->n0;
+    const int64_t n = h->n0, nl = h->nl0;
     if (op >= FVEM_OP_PI1 && op <= FVEM_OP_AVT) check(h->ncell_v > 0, "no velocity operators in this hierarchy");
     if (acc)
       check(op == FVEM_OP_BT || op == FVEM_OP_PI1 || op == FVEM_OP_PI1T || op == FVEM_OP_G || op == FVEM_OP_MASS ||
@@ -1182,7 +1357,7 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
       case FVEM_OP_PI1: csr(h->Pi, x); break;
       case FVEM_OP_PI1T: csr(h->PiT, x); break;
       case FVEM_OP_G:
-        gather(n, h->perm0, x, h->p, s);
+        gather(nl, h->perm0, x, h->p, s);
         csr(h->Gr, h->p);
         break;
       case FVEM_OP_GT:
@@ -1193,7 +1368,7 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
       case FVEM_OP_AV: csr(h->Av, x); break;
       case FVEM_OP_AVT: csr(h->AvT, x); break;
       case FVEM_OP_K:
-        gather(n, h->perm0, x, h->p, s);
+        gather(nl, h->perm0, x, h->p, s);
         spmv<double>(h->lv[0].A.d(), h->p, h->q, s);
         gather(n, h->iperm0, h->q, y, s);
         break;
@@ -1204,12 +1379,12 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
         break;
       case FVEM_OP_BT:
         check(h->nvert > 0, "no divergence operator");
-        gather(n, h->perm0, x, h->p, s);
+        gather(nl, h->perm0, x, h->p, s);
         csr(h->BT, h->p);
         break;
       case FVEM_OP_VCYCLE:
       case FVEM_OP_VCYCLE32: {
-        gather(n, h->perm0, x, h->r, s);
+        gather(nl, h->perm0, x, h->r, s);
         double nr = 1.0;
         if (op == FVEM_OP_VCYCLE32) {
           double d[1];
@@ -1221,8 +1396,8 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
         break;
       }
       case FVEM_OP_PROJECT:
-        gather(n, h->perm0, x, h->z, s);
-        if (h->ncomp0) project_components(n, h->z, h->comp0, h->ncomp0, h->partial, h->mean, s);
+        gather(nl, h->perm0, x, h->z, s);
+        if (h->ncomp0) project_components(nl, h->z, h->comp0, h->ncomp0, h->partial, h->mean, s);
         gather(n, h->iperm0, h->z, y, s);
         break;
       default: throw SetupError{FVEM_ERR_INVALID, "unknown operator"};
@@ -1266,8 +1441,8 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
   }
   return guard([&] {
     const DevSELL &A = h->lv[level].A;
-    if (n_rows) *n_rows = A.n;
-    if (nnz) *nnz = A.nnz;
+    if (n_rows) *n_rows = level == 0 ? h->n0 : A.n;
+    if (nnz) *nnz = A.nnz + A.st.nnz;
     if (!row_ptr && !col && !val) return FVEM_OK;
     // read back the sliced operator and return it in the caller's order
     HostSELL S;
@@ -1290,7 +1465,50 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
     if (A.d64.nvals)
       HIPCHECK(hipMemcpy(S.v64.v.data(), A.v64, sizeof(double) * A.d64.nvals, hipMemcpyDeviceToHost));
     const std::vector<int32_t> &order = h->lv[level].order;
-    const HostCSR C = permute(from_sell(S), inverse(order), &order);
+    HostCSR Ls = from_sell(S);
+    if (!A.hrowmap.empty() || A.st.ntiles > 0) {
+      // sliced rows scattered to their level rows, plus the stencil rows
+      const int64_t nl = h->lv[level].n;
+      const auto &L = A.st.host;
+      std::vector<std::vector<std::pair<int32_t, double>>> rows(nl);
+      for (int64_t k = 0; k < Ls.n_rows; ++k)
+        for (int64_t q = Ls.rp[k]; q < Ls.rp[k + 1]; ++q) rows[A.hrowmap[k]].emplace_back(Ls.ci[q], Ls.v[q]);
+      const int tn = L.tn;
+      for (size_t b = 0; b < L.tiles.size(); ++b) {
+        const int32_t T = L.tiles[b];
+        const int Ta = T / (tn * tn), Tb = (T / tn) % tn, Tc = T % tn;
+        for (int t = 0; t < 8; ++t)
+          for (int lane = 0; lane < 64; ++lane) {
+            if (!((L.mask[8 * b + t] >> lane) & 1)) continue;
+            const int a0 = 8 * Ta + (t >> 2) + 2 * (lane >> 4), b0 = 8 * Tb + ((t >> 1) & 1) + 2 * ((lane >> 2) & 3),
+                      c0 = 8 * Tc + (t & 1) + 2 * (lane & 3);
+            auto &row = rows[L.tile_base[T] + 64 * t + lane];
+            for (int j = 0; j < L.len[t]; ++j) {
+              const int q = L.delta[128 * t + j];
+              const int a = a0 + q / 25 - 2, bb = b0 + (q / 5) % 5 - 2, c = c0 + q % 5 - 2;
+              const int32_t base = L.tile_base[((a >> 3) * tn + (bb >> 3)) * tn + (c >> 3)];
+              const int cls = 4 * (a & 1) + 2 * (bb & 1) + (c & 1);
+              row.emplace_back(base + 64 * cls + 16 * ((a & 7) >> 1) + 4 * ((bb & 7) >> 1) + ((c & 7) >> 1),
+                               L.val[128 * t + j]);
+            }
+          }
+      }
+      HostCSR P;
+      P.n_rows = nl;
+      P.n_cols = nl;
+      P.rp.assign(nl + 1, 0);
+      for (int64_t r = 0; r < nl; ++r) P.rp[r + 1] = P.rp[r] + static_cast<int64_t>(rows[r].size());
+      P.ci.resize(P.rp[nl]);
+      P.v.resize(P.rp[nl]);
+      for (int64_t r = 0; r < nl; ++r)
+        for (size_t q = 0; q < rows[r].size(); ++q) {
+          P.ci[P.rp[r] + q] = rows[r][q].first;
+          P.v[P.rp[r] + q] = rows[r][q].second;
+        }
+      Ls = std::move(P);
+    }
+    const int64_t ncaller = level == 0 ? h->n0 : h->lv[level].n;
+    const HostCSR C = permute(Ls, inverse(order, ncaller), &order, ncaller);
     if (row_ptr) std::copy(C.rp.begin(), C.rp.end(), row_ptr);
     if (col) std::copy(C.ci.begin(), C.ci.end(), col);
     if (val) std::copy(C.v.begin(), C.v.end(), val);
@@ -1314,6 +1532,7 @@ fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n
 void fvem_hierarchy_destroy(fvem_hierarchy *h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->evv) (void)hipEventDestroy(e);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
 }
@@ -1326,6 +1545,8 @@ struct fvem_grid {
   fvem::grid::Output out;
   std::vector<fvem_level_desc> levels;
   std::vector<double> xflat;
+  std::vector<int32_t> lat;   // lattice coordinates of the level-0 DOFs (-1: off the lattice)
+  int32_t lat_n = 0;
 };
 
 extern "C" {
@@ -1382,6 +1603,26 @@ fvem_status fvem_grid_build(const double *V, int64_t nv, const int32_t *F, int64
         d.P.val = P.v.data();
       }
     }
+    {
+      // support points on the background lattice: the half-lattice of
+      // spacing h/2 for k = 2 (vertices, edge midpoints, face and cell
+      // centres of uncut cubes), the vertex lattice for k = 1
+      const auto &L0 = o.levels[0];
+      const double scale = k == 2 ? 2.0 * N : static_cast<double>(N);
+      g->lat_n = static_cast<int32_t>(scale) + 1;
+      g->lat.assign(3 * L0.n_dof, -1);
+      for (int64_t i = 0; i < L0.n_dof; ++i) {
+        int32_t c[3];
+        bool on = true;
+        for (int d = 0; d < 3 && on; ++d) {
+          const double q = L0.dof_point[3 * i + d] * scale, r = std::nearbyint(q);
+          on = std::fabs(q - r) < 1e-7 && r >= 0 && r < g->lat_n;
+          c[d] = static_cast<int32_t>(r);
+        }
+        if (on)
+          for (int d = 0; d < 3; ++d) g->lat[3 * i + d] = c[d];
+      }
+    }
     g->xflat.resize(3 * o.X.size());
     for (size_t i = 0; i < o.X.size(); ++i) {
       g->xflat[3 * i] = o.X[i].x;
@@ -1417,6 +1658,8 @@ fvem_status fvem_grid_describe(fvem_grid *g, fvem_grid_desc *d) {
   d->vc_len = static_cast<int64_t>(o.vc_val.size());
   d->cell_geom = o.cell_geom.data();
   d->vert_xyz = g->xflat.data();
+  d->dof_lattice = g->lat.empty() ? nullptr : g->lat.data();
+  d->lattice_n = g->lat_n;
   return FVEM_OK;
 }
 

@@ -126,7 +126,7 @@ template void cheb_first<float>(int64_t, const float *, const float *, float *, 
 __global__ void gather_kernel(int64_t n, const int32_t *idx, const double *x, double *y) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    y[i] = x[idx[i]];
+    y[i] = idx[i] >= 0 ? x[idx[i]] : 0.0;
 }
 
 void gather(int64_t n, const int32_t *idx, const double *x, double *y, hipStream_t s) {

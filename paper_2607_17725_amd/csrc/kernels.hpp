@@ -17,6 +17,22 @@ struct DevCSRView {
   const T *v = nullptr;
 };
 
+// Lattice stencil rows of a level operator (see HostLattice in
+// setup_host.hpp): one workgroup per tile listed in tiles; x of the tile
+// plus a 2-point halo is staged in LDS by class, and each wavefront applies
+// its class's table to the slots flagged in the tile's mask.
+template <typename T>
+struct StencilView {
+  int64_t ntiles = 0;
+  const int32_t *tiles = nullptr;      // tile ids, launch order
+  const uint64_t *mask = nullptr;      // 8 words per launched tile
+  const int32_t *tile_base = nullptr;  // tn^3 slot bases (-1: no slots)
+  int32_t tn = 0, lat_n = 0;
+  const int32_t *len = nullptr;        // 8 entry counts
+  const int32_t *off = nullptr;        // 8 x 128 LDS offsets
+  const T *val = nullptr;              // 8 x 128 values
+};
+
 // Sliced ELLPACK with 64-row slices (one wavefront lane per row).  Slice s
 // holds rows [64 s, 64 s + 64); entry j of lane r sits at o = 256 (j / 4) +
 // 4 r + j % 4 from the slice's start, for j < sl[s] (the slice's longest row
@@ -41,6 +57,7 @@ struct DevSELLView {
   int32_t tw = 0;
   bool split = false;   // several lanes per row (small levels)
   const int32_t *rowmap = nullptr;   // stored row r is output row rowmap[r] (null: r)
+  StencilView<T> st;    // lattice stencil rows applied before the sliced rows (ntiles 0: none)
 };
 
 // SpMV family on the sliced layout (level operators; fused epilogues)
@@ -62,7 +79,7 @@ void cheb_step(const DevCSRView<T> &A, const T *b, const T *dinv, const T *xin, 
 template <typename T> void cheb_first(int64_t n, const T *b, const T *dinv, T *d, T *x, T cb, hipStream_t s);
 
 // vectors
-void gather(int64_t n, const int32_t *idx, const double *x, double *y, hipStream_t s);   // y[i] = x[idx[i]]
+void gather(int64_t n, const int32_t *idx, const double *x, double *y, hipStream_t s);   // y[i] = x[idx[i]] (0 where idx[i] < 0)
 // y = alpha a + beta b (b may be null: y = alpha a); y may alias a or b
 void lincomb(int64_t n, double alpha, const double *a, double beta, const double *b, double *y, hipStream_t s);
 void cast_scale(int64_t n, const double *a, float *b, double s, hipStream_t st);

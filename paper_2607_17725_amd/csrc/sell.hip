@@ -5,6 +5,7 @@
 
 #include "epilogues.hpp"
 #include "kernels.hpp"
+#include "setup_host.hpp"
 
 namespace fvem {
 
@@ -207,8 +208,52 @@ __global__ __launch_bounds__(256) void sell_split_kernel(
   if (k == 0) epi(rowmap ? static_cast<int64_t>(rowmap[row]) : row, acc);
 }
 
+// Lattice stencil rows.  One workgroup of 8 wavefronts per tile; wavefront
+// t handles the 64 slots of class t.  The tile's 8^3 points plus a 2-point
+// halo (12^3 = 1728 values) are staged in LDS, split by class into 6^3
+// sub-grids whose pitches (8 per row, 68 per plane) keep the 32 lanes of a
+// half-wavefront on distinct banks.  The class table (LDS offset, value) is
+// wave-uniform, so its entries come through scalar loads; every lane sums its
+// entries in the table's fixed order (deterministic).
+template <typename VT, typename XT, class Epi>
+__global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const XT *__restrict__ x, Epi epi) {
+  __shared__ XT halo[8 * STENCIL_SUB];
+  const int64_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int32_t tile = st.tiles[b];
+  const int tn = st.tn, N = st.lat_n;
+  const int Ta = tile / (tn * tn), Tb = (tile / tn) % tn, Tc = tile % tn;
+  for (int e = threadIdx.x; e < 1728; e += 512) {
+    const int tp = e / 216, r = e - 216 * tp;
+    const int I = r / 36, J = (r / 6) % 6, K = r % 6;
+    const int a = 8 * Ta - 2 + (tp >> 2) + 2 * I;
+    const int bb = 8 * Tb - 2 + ((tp >> 1) & 1) + 2 * J;
+    const int c = 8 * Tc - 2 + (tp & 1) + 2 * K;
+    XT v = 0;
+    if (a >= 0 && a < N && bb >= 0 && bb < N && c >= 0 && c < N) {
+      const int32_t base = st.tile_base[((a >> 3) * tn + (bb >> 3)) * tn + (c >> 3)];
+      if (base >= 0) v = x[base + 64 * tp + 16 * ((a & 7) >> 1) + 4 * ((bb & 7) >> 1) + ((c & 7) >> 1)];
+    }
+    halo[tp * STENCIL_SUB + I * STENCIL_P1 + J * STENCIL_P2 + K] = v;
+  }
+  __syncthreads();
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const uint64_t m = st.mask[8 * b + t];
+  if (!((m >> lane) & 1)) return;
+  const XT *hp = halo + (lane >> 4) * STENCIL_P1 + ((lane >> 2) & 3) * STENCIL_P2 + (lane & 3);
+  const int len = st.len[t];
+  const int32_t *off = st.off + 128 * t;
+  const VT *val = st.val + 128 * t;
+  using AT = typename Epi::acc_t;
+  AT acc = 0;
+  for (int j = 0; j < len; ++j) acc += static_cast<AT>(val[j]) * static_cast<AT>(hp[off[j]]);
+  epi(static_cast<int64_t>(st.tile_base[tile]) + 64 * t + lane, acc);
+}
+
 template <typename VT, typename XT, class Epi>
 static void launch_sell(const DevSELLView<VT> &A, const XT *x, Epi epi, hipStream_t s) {
+  if (A.st.ntiles > 0)
+    stencil_kernel<VT, XT, Epi><<<static_cast<unsigned>(A.st.ntiles), 512, 0, s>>>(A.st, x, epi);
   if (A.nslices == 0) return;
   if (A.split) {
     const dim3 grid(static_cast<unsigned>((A.n * SELL_SPLIT + 255) / 256));

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <numeric>
 #include <unordered_map>
+#include <cstdio>
 #include <omp.h>
 
 namespace fvem {
@@ -232,16 +233,19 @@ std::vector<int32_t> window_order(const HostCSR &A, int64_t w) {
   return order;
 }
 
-HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::vector<int32_t> *col_map) {
+HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::vector<int32_t> *col_map,
+                int64_t n_cols) {
   HostCSR B;
-  B.n_rows = A.n_rows;
-  B.n_cols = A.n_cols;
+  B.n_rows = static_cast<int64_t>(order.size());
+  B.n_cols = n_cols >= 0 ? n_cols : A.n_cols;
   B.rp.assign(B.n_rows + 1, 0);
-  for (int64_t r = 0; r < B.n_rows; ++r) B.rp[r + 1] = B.rp[r] + (A.rp[order[r] + 1] - A.rp[order[r]]);
-  B.ci.resize(A.nnz());
-  B.v.resize(A.nnz());
+  for (int64_t r = 0; r < B.n_rows; ++r)
+    B.rp[r + 1] = B.rp[r] + (order[r] < 0 ? 0 : A.rp[order[r] + 1] - A.rp[order[r]]);
+  B.ci.resize(B.rp[B.n_rows]);
+  B.v.resize(B.rp[B.n_rows]);
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t r = 0; r < B.n_rows; ++r) {
+    if (order[r] < 0) continue;
     const int64_t o = order[r], len = A.rp[o + 1] - A.rp[o];
     thread_local std::vector<std::pair<int32_t, double>> e;
     e.resize(len);
@@ -467,6 +471,197 @@ HostCSR from_sell(const HostSELL &S) {
     }
   }
   return A;
+}
+
+namespace {
+
+inline uint64_t mix64(uint64_t z) {   // SplitMix64 finaliser
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+inline uint64_t morton3(uint32_t a, uint32_t b, uint32_t c) {
+  uint64_t m = 0;
+  for (int i = 0; i < 21; ++i)
+    m |= ((uint64_t(a >> i) & 1) << (3 * i + 2)) | ((uint64_t(b >> i) & 1) << (3 * i + 1)) |
+         ((uint64_t(c >> i) & 1) << (3 * i));
+  return m;
+}
+
+}  // namespace
+
+bool lattice_layout(const HostCSR &A, const int32_t *lat, int32_t lat_n, double min_fraction, HostLattice *L) {
+  *L = HostLattice();
+  const int64_t n = A.n_rows;
+  if (!lat || lat_n < 3 || n == 0) return false;
+  const int64_t ln = lat_n, ln3 = ln * ln * ln;
+  // point -> DOF; a point claimed twice leaves the lattice for both DOFs
+  std::vector<int32_t> pt(ln3, -1);
+  std::vector<uint8_t> on(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t a = lat[3 * i], b = lat[3 * i + 1], c = lat[3 * i + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= lat_n || b >= lat_n || c >= lat_n) continue;
+    int32_t &q = pt[(a * ln + b) * ln + c];
+    if (q == -1) {
+      q = static_cast<int32_t>(i);
+      on[i] = 1;
+    } else {
+      if (q >= 0) on[q] = 0;
+      q = -2;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (on[i] && pt[(lat[3 * i] * ln + lat[3 * i + 1]) * ln + lat[3 * i + 2]] != i) on[i] = 0;
+  auto cls = [&](int64_t i) { return 4 * (lat[3 * i] & 1) + 2 * (lat[3 * i + 1] & 1) + (lat[3 * i + 2] & 1); };
+  // dense stencil of a row in offset space; false if some column is off the lattice or too far
+  auto dense = [&](int64_t i, double *v, uint8_t *p) {
+    std::fill(p, p + STENCIL_MAX, 0);
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      if (!on[j]) return false;
+      const int da = lat[3 * j] - lat[3 * i], db = lat[3 * j + 1] - lat[3 * i + 1], dc = lat[3 * j + 2] - lat[3 * i + 2];
+      if (da < -2 || da > 2 || db < -2 || db > 2 || dc < -2 || dc > 2) return false;
+      const int code = (da + 2) * 25 + (db + 2) * 5 + (dc + 2);
+      v[code] = A.v[k];
+      p[code] = 1;
+    }
+    return true;
+  };
+  auto hash = [&](const double *v, const uint8_t *p) {
+    uint64_t hsh = 0x12345;
+    for (int q = 0; q < STENCIL_MAX; ++q)
+      if (p[q]) {
+        uint64_t bits;
+        std::memcpy(&bits, &v[q], 8);
+        hsh = mix64(hsh ^ (static_cast<uint64_t>(q) << 56) ^ mix64(bits));
+      }
+    return hsh;
+  };
+  std::vector<uint64_t> rh(n, 0);
+  std::vector<uint8_t> elig(n, 0);
+#pragma omp parallel
+  {
+    double v[STENCIL_MAX];
+    uint8_t p[STENCIL_MAX];
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n; ++i) {
+      if (!on[i] || !dense(i, v, p)) continue;
+      elig[i] = 1;
+      rh[i] = hash(v, p);
+    }
+  }
+  // reference stencil of each class: its most frequent row (at least 64 rows)
+  int64_t ref_row[8];
+  for (int t = 0; t < 8; ++t) {
+    std::unordered_map<uint64_t, std::pair<int64_t, int64_t>> cnt;   // hash -> (count, first row)
+    for (int64_t i = 0; i < n; ++i)
+      if (elig[i] && cls(i) == t) {
+        auto it = cnt.find(rh[i]);
+        if (it == cnt.end()) cnt.emplace(rh[i], std::make_pair(int64_t(1), i));
+        else ++it->second.first;
+      }
+    ref_row[t] = -1;
+    int64_t best = 63;
+    for (const auto &kv : cnt)
+      if (kv.second.first > best || (kv.second.first == best && ref_row[t] >= 0 && kv.second.second < ref_row[t])) {
+        best = kv.second.first;
+        ref_row[t] = kv.second.second;
+      }
+  }
+  std::vector<double> rv(8 * STENCIL_MAX, 0.0);
+  std::vector<uint8_t> rp(8 * STENCIL_MAX, 0);
+  for (int t = 0; t < 8; ++t)
+    if (ref_row[t] >= 0) dense(ref_row[t], &rv[STENCIL_MAX * t], &rp[STENCIL_MAX * t]);
+  L->is_stencil.assign(n, 0);
+  int64_t nst = 0, nnzst = 0;
+#pragma omp parallel
+  {
+    double v[STENCIL_MAX];
+    uint8_t p[STENCIL_MAX];
+#pragma omp for schedule(dynamic, 4096) reduction(+ : nst, nnzst)
+    for (int64_t i = 0; i < n; ++i) {
+      if (!elig[i]) continue;
+      const int t = cls(i);
+      if (ref_row[t] < 0 || rh[i] != rh[ref_row[t]]) continue;
+      dense(i, v, p);
+      bool same = true;
+      for (int q = 0; q < STENCIL_MAX && same; ++q)
+        same = p[q] == rp[STENCIL_MAX * t + q] && (!p[q] || std::memcmp(&v[q], &rv[STENCIL_MAX * t + q], 8) == 0);
+      if (!same) continue;
+      L->is_stencil[i] = 1;
+      ++nst;
+      nnzst += A.rp[i + 1] - A.rp[i];
+    }
+  }
+  if (static_cast<double>(nst) < min_fraction * static_cast<double>(n)) {
+    *L = HostLattice();
+    return false;
+  }
+  L->n_stencil = nst;
+  L->nnz_stencil = nnzst;
+  L->lat_n = lat_n;
+  const int32_t tn = (lat_n + 7) / 8;
+  L->tn = tn;
+  const int64_t tn3 = static_cast<int64_t>(tn) * tn * tn;
+  // tiles holding a lattice DOF, in Morton order
+  std::vector<uint8_t> used(tn3, 0);
+  for (int64_t i = 0; i < n; ++i)
+    if (on[i]) used[((lat[3 * i] >> 3) * tn + (lat[3 * i + 1] >> 3)) * tn + (lat[3 * i + 2] >> 3)] = 1;
+  std::vector<std::pair<uint64_t, int32_t>> mt;
+  for (int64_t t = 0; t < tn3; ++t)
+    if (used[t]) mt.emplace_back(morton3(t / (tn * tn), (t / tn) % tn, t % tn), static_cast<int32_t>(t));
+  std::sort(mt.begin(), mt.end());
+  L->tile_base.assign(tn3, -1);
+  for (size_t r = 0; r < mt.size(); ++r) L->tile_base[mt[r].second] = static_cast<int32_t>(512 * r);
+  const int64_t nslot = 512 * static_cast<int64_t>(mt.size());
+  if (nslot + n >= (int64_t(1) << 31)) {
+    *L = HostLattice();
+    return false;
+  }
+  L->order.assign(nslot, -1);
+  std::vector<uint64_t> tmask(8 * mt.size(), 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!on[i]) continue;
+    const int a = lat[3 * i], b = lat[3 * i + 1], c = lat[3 * i + 2];
+    const int64_t tile = ((a >> 3) * tn + (b >> 3)) * tn + (c >> 3);
+    const int t = cls(i);
+    const int pos = 16 * ((a & 7) >> 1) + 4 * ((b & 7) >> 1) + ((c & 7) >> 1);
+    const int64_t slot = L->tile_base[tile] + 64 * t + pos;
+    L->order[slot] = static_cast<int32_t>(i);
+    if (L->is_stencil[i]) tmask[8 * (L->tile_base[tile] / 512) + t] |= uint64_t(1) << pos;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (!on[i]) L->order.push_back(static_cast<int32_t>(i));
+  for (size_t r = 0; r < mt.size(); ++r) {
+    bool any = false;
+    for (int t = 0; t < 8; ++t) any = any || tmask[8 * r + t];
+    if (!any) continue;
+    L->tiles.push_back(mt[r].second);
+    for (int t = 0; t < 8; ++t) L->mask.push_back(tmask[8 * r + t]);
+  }
+  // class tables: entries in increasing offset code; LDS offsets into the
+  // class-major 6x6x6 halo of the neighbour's class
+  L->off.assign(8 * 128, 0);
+  L->delta.assign(8 * 128, 0);
+  L->val.assign(8 * 128, 0.0);
+  for (int t = 0; t < 8; ++t) {
+    int m = 0;
+    const int ta = t >> 2, tb = (t >> 1) & 1, tc = t & 1;
+    for (int q = 0; q < STENCIL_MAX; ++q) {
+      if (!rp[STENCIL_MAX * t + q]) continue;
+      const int da = q / 25 - 2, db = (q / 5) % 5 - 2, dc = q % 5 - 2;
+      const int ua = (ta + da) & 1, ub = (tb + db) & 1, uc = (tc + dc) & 1;
+      const int ea = (ta + da + 2 - ua) / 2, eb = (tb + db + 2 - ub) / 2, ec = (tc + dc + 2 - uc) / 2;
+      L->off[128 * t + m] = (4 * ua + 2 * ub + uc) * STENCIL_SUB + ea * STENCIL_P1 + eb * STENCIL_P2 + ec;
+      L->delta[128 * t + m] = q;
+      L->val[128 * t + m] = rv[STENCIL_MAX * t + q];
+      ++m;
+    }
+    L->len[t] = m;
+  }
+  return true;
 }
 
 double gershgorin_scaled(const HostCSR &A) {

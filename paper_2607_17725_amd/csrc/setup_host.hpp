@@ -62,8 +62,11 @@ HostCSR transpose(const HostCSR &A);
 std::vector<int32_t> window_order(const HostCSR &A, int64_t w);
 
 // B = rows order[r] of A with columns renamed by col_map (old -> new; null
-// keeps them), columns sorted ascending within each row.
-HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::vector<int32_t> *col_map);
+// keeps them), columns sorted ascending within each row.  order may be
+// longer than A's row count and hold -1 (empty rows); n_cols < 0 keeps A's
+// column count.
+HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::vector<int32_t> *col_map,
+                int64_t n_cols = -1);
 
 // Sliced ELLPACK with 64-row slices, interleaved in groups of 4 entries:
 // entry j of row 64 s + r sits at sp[s] + 256 (j / 4) + 4 r + j % 4, so a
@@ -114,6 +117,44 @@ struct HostSELL {
 HostSELL to_sell(const HostCSR &A, bool templates = false, int min_uses = 64, int max_templates = 1024,
                  bool codes = false);
 HostCSR from_sell(const HostSELL &S);   // FP64 values
+
+// Lattice stencil part of a level operator (compact storage of regular
+// regions).  Away from cut cells every row of a DOF on the structured
+// lattice (half-lattice of spacing h/2 for k = 2) is the same stencil up to
+// translation, one stencil per parity class of the lattice coordinates.
+// Such rows need no column or value storage: their columns follow from the
+// lattice position, their values from one table per class.
+//
+// Level vectors are laid out by 8x8x8-point lattice tiles: every tile that
+// holds a DOF gets 512 slots, class-major (8 classes of 4x4x4 points, the
+// class of (a, b, c) being 4 (a & 1) + 2 (b & 1) + (c & 1)), so the slot of
+// point (a, b, c) is tile_base[tile] + 64 class + 16 ((a & 7) >> 1) +
+// 4 ((b & 7) >> 1) + ((c & 7) >> 1).  Slots without a DOF are holes (zero in
+// every vector); DOFs off the lattice follow the slots.  A stencil kernel
+// loads a tile's x plus a 2-point halo into LDS and applies the class
+// tables; the other rows go to the sliced storage.
+constexpr int STENCIL_MAX = 125;        // 5x5x5 offsets (|delta| <= 2 per axis)
+constexpr int STENCIL_P2 = 8;           // LDS pitch of a halo row (6 points)
+constexpr int STENCIL_P1 = 68;          // LDS pitch of a halo plane (6 rows)
+constexpr int STENCIL_SUB = 6 * STENCIL_P1;   // LDS size of one class's 6^3 halo
+struct HostLattice {
+  int32_t lat_n = 0, tn = 0;         // lattice points and tiles per axis
+  std::vector<int32_t> order;        // padded level order: order[slot] = DOF or -1
+  std::vector<int32_t> tile_base;    // tn^3: first slot of each tile or -1
+  std::vector<int32_t> tiles;        // tiles holding stencil rows (launch order)
+  std::vector<uint64_t> mask;        // 8 words per entry of tiles: stencil slots
+  std::vector<uint8_t> is_stencil;   // per DOF (caller order)
+  int32_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<int32_t> off;          // 8 x 128: LDS offset of each stencil entry
+  std::vector<int32_t> delta;        // 8 x 128: lattice offset code (da+2)*25+(db+2)*5+(dc+2)
+  std::vector<double> val;           // 8 x 128: entry values
+  int64_t n_stencil = 0, nnz_stencil = 0;
+};
+// Builds the layout from the assembled operator A (rows and columns in the
+// caller's DOF order) and the lattice coordinates lat [n x 3] of its DOFs
+// (-1: off the lattice).  Returns false (and leaves *L empty) when fewer than
+// min_fraction of the rows are stencil rows.
+bool lattice_layout(const HostCSR &A, const int32_t *lat, int32_t lat_n, double min_fraction, HostLattice *L);
 
 // max_i sum_j |a_ij| / sqrt(a_ii a_jj): Gershgorin bound of D^-1/2 A D^-1/2,
 // which has the spectrum of D^-1 A and stays bounded by the row length for

@@ -48,14 +48,15 @@ class _Grid(ctypes.Structure):
                 ("be_off", ctypes.c_void_p), ("be_val", ctypes.c_void_p), ("be_len", ctypes.c_int64),
                 ("component", ctypes.c_void_p), ("n_components", ctypes.c_int32),
                 ("vc_off", ctypes.c_void_p), ("vc_val", ctypes.c_void_p), ("vc_len", ctypes.c_int64),
-                ("cell_geom", ctypes.c_void_p), ("vert_xyz", ctypes.c_void_p)]
+                ("cell_geom", ctypes.c_void_p), ("vert_xyz", ctypes.c_void_p),
+                ("dof_lattice", ctypes.c_void_p), ("lattice_n", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
     _fields_ = [("cheb_degree", ctypes.c_int32), ("cheb_lower", ctypes.c_double),
                 ("coarse_dense_max", ctypes.c_int32), ("coarse_rcond", ctypes.c_double),
                 ("coarse_shift", ctypes.c_double), ("small_level_rows", ctypes.c_int64),
-                ("max_templates", ctypes.c_int32)]
+                ("max_templates", ctypes.c_int32), ("lattice_min_fraction", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -66,7 +67,7 @@ class SolveOpts(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_fine_smoother", ctypes.c_double), ("n_fine_smoother", ctypes.c_int32),
-                ("n_levels", ctypes.c_int32)]
+                ("n_levels", ctypes.c_int32), ("ms_vcycle", ctypes.c_double), ("n_vcycle", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -76,7 +77,8 @@ EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_app
            "fvem_hierarchy_info", "fvem_hierarchy_destroy", "fvem_last_error", "fvem_grid_build",
            "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy",
            "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells",
-           "fvem_level_storage", "fvem_level_bytes", "fvem_project_noalloc"]
+           "fvem_level_storage", "fvem_level_bytes", "fvem_project_noalloc", "fvem_level_stencil",
+           "fvem_transfer_storage", "fvem_vcycle_bytes"]
 
 _lib = None
 
@@ -111,6 +113,13 @@ def load(path=LIB_PATH):
     lib.fvem_level_bytes.restype = ctypes.c_int
     lib.fvem_hierarchy_cells.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fvem_hierarchy_cells.restype = ctypes.c_int
+    lib.fvem_transfer_storage.argtypes = [vp, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                          ctypes.POINTER(i64)]
+    lib.fvem_transfer_storage.restype = ctypes.c_int
+    lib.fvem_vcycle_bytes.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.fvem_vcycle_bytes.restype = ctypes.c_int
+    lib.fvem_level_stencil.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.fvem_level_stencil.restype = ctypes.c_int
     lib.fvem_project_noalloc.argtypes = [vp, vp, vp, vp]
     lib.fvem_project_noalloc.restype = ctypes.c_int
     lib.fvem_level_matrix.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
@@ -162,7 +171,8 @@ class Hierarchy:
     """
 
     def __init__(self, desc, stream=None, cheb_degree=5, cheb_lower=1.0 / 30.0, coarse_dense_max=16384,
-                 coarse_rcond=0.0, coarse_shift=1e-8, small_level_rows=0, max_templates=0):
+                 coarse_rcond=0.0, coarse_shift=1e-8, small_level_rows=0, max_templates=0,
+                 lattice_min_fraction=0.0):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -171,7 +181,7 @@ class Hierarchy:
             g = _Grid()
             _check(lib.fvem_grid_describe(desc._g, ctypes.byref(g)))
             self._finish(lib, g, [desc], stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond,
-                         coarse_shift, small_level_rows, max_templates)
+                         coarse_shift, small_level_rows, max_templates, lattice_min_fraction)
             return
         keep = []
         L = len(desc["levels"])
@@ -201,7 +211,7 @@ class Hierarchy:
         for name, dt in (("ke_off", np.int64), ("ke_val", np.float64), ("cell_vptr", np.int64),
                          ("cell_vert", np.int32), ("be_off", np.int64), ("be_val", np.float64),
                          ("component", np.int32), ("vc_off", np.int64), ("vc_val", np.float64),
-                         ("cell_geom", np.float64), ("vert_xyz", np.float64)):
+                         ("cell_geom", np.float64), ("vert_xyz", np.float64), ("dof_lattice", np.int32)):
             if desc.get(name) is not None:
                 a, p = _arr(desc[name], dt)
                 keep.append(a)
@@ -211,14 +221,15 @@ class Hierarchy:
         g.vc_len = len(desc["vc_val"]) if desc.get("vc_val") is not None else 0
         g.n_vert = int(desc.get("n_vert", 0))
         g.n_components = int(desc.get("n_components", 0))
+        g.lattice_n = int(desc.get("lattice_n", 0))
         self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                     small_level_rows, max_templates)
+                     small_level_rows, max_templates, lattice_min_fraction)
 
     def _finish(self, lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                small_level_rows, max_templates):
+                small_level_rows, max_templates, lattice_min_fraction):
         import torch
         opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift, small_level_rows,
-                        max_templates)
+                        max_templates, lattice_min_fraction)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         _check(lib.fvem_hierarchy_build(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
@@ -349,11 +360,38 @@ class Hierarchy:
         return dict(zip(("nnz", "nnz_explicit", "rows_templated", "n_templates", "template_width"),
                         (x.value for x in v)))
 
+    def transfer_storage(self, level, precision=PREC_MIXED):
+        """P_level nonzeros and the matrix bytes of one application of P_level and R_level."""
+        v = [ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()]
+        _check(load().fvem_transfer_storage(self._h, level, precision, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("nnz", "bytes_p", "bytes_r"), (x.value for x in v)))
+
+    def transfer_nnz(self, level):
+        return self.transfer_storage(level)["nnz"]
+
+    def vcycle_bytes(self, precision=PREC_MIXED):
+        """Algorithmic bytes of one V-cycle (fvem_vcycle_bytes)."""
+        b = ctypes.c_int64()
+        _check(load().fvem_vcycle_bytes(self._h, precision, ctypes.byref(b)))
+        return b.value
+
+    def level_stencil(self, level):
+        """Lattice stencil part of level ``level``'s operator: rows, nnz, tiles."""
+        v = [ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()]
+        _check(load().fvem_level_stencil(self._h, level, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("rows", "nnz", "tiles"), (x.value for x in v)))
+
     def level_bytes(self, level, precision=PREC_MIXED):
         """Matrix bytes one application of level ``level``'s operator reads (see fvem_level_bytes)."""
         b = ctypes.c_int64()
         _check(load().fvem_level_bytes(self._h, level, precision, ctypes.byref(b)))
         return b.value
+
+    def level_rows(self, level):
+        """DOFs (rows) of level ``level``'s operator."""
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().fvem_level_matrix(self._h, level, ctypes.byref(n), ctypes.byref(nnz), None, None, None))
+        return n.value
 
     def level_matrix(self, level):
         """Level operator as (row_ptr, col, val) host arrays."""
@@ -437,7 +475,10 @@ class Grid:
                 "n_components": g.n_components,
                 "vc_off": arr(g.vc_off, nc0, ctypes.c_int64), "vc_val": arr(g.vc_val, g.vc_len, ctypes.c_double),
                 "cell_geom": arr(g.cell_geom, 5 * nc0, ctypes.c_double),
-                "vert_xyz": arr(g.vert_xyz, 3 * g.n_vert, ctypes.c_double)}
+                "vert_xyz": arr(g.vert_xyz, 3 * g.n_vert, ctypes.c_double),
+                "dof_lattice": (arr(g.dof_lattice, 3 * g.levels[0].n_dof, ctypes.c_int32)
+                                if g.dof_lattice else None),
+                "lattice_n": g.lattice_n}
 
     def __del__(self):
         g = getattr(self, "_g", None)

@@ -18,7 +18,48 @@ def level_cells(pb, level):
     return np.array(ptr, dtype=np.int64), np.array(dof, dtype=np.int32)
 
 
-def describe(pb):
+def _canonical_cube_blocks(pb, blocks):
+    """Give every uncut cube of one size the same stiffness block.
+
+    The oracle computes each cell's K^E on its own; cubes of equal size then
+    differ only by rounding.  Using one computed block for all of them (each
+    reordered to the cube's local DOF order by support point) makes
+    translated rows of the assembled operator bitwise equal, as the native
+    builder's shared blocks do.
+    """
+    m, d = pb.meshes[0], pb.dofs[0]
+    full = _all_points(pb)
+    ref = {}
+    for c in range(len(m.cell_faces)):
+        vts = m.X[m.cell_verts[c]]
+        lo, hi = vts.min(axis=0), vts.max(axis=0)
+        ext = hi - lo
+        if len(m.cell_verts[c]) != 8 or len(m.cell_faces[c]) != 6 or not np.allclose(ext, ext[0], rtol=0, atol=1e-14) \
+                or abs(m.cell_volume[c] - ext.prod()) > 1e-14 * ext.prod():
+            continue
+        key = round(float(ext[0]) * 2 ** 40)
+        rel = np.rint((full[d.cell_dofs(c)] - lo) / ext[0] * 4).astype(int)
+        keys = [tuple(r) for r in rel]
+        if key not in ref:
+            ref[key] = (blocks[c], {k: i for i, k in enumerate(keys)})
+            continue
+        B0, idx = ref[key]
+        perm = [idx[k] for k in keys]
+        blocks[c] = B0[np.ix_(perm, perm)]
+    return blocks
+
+
+def _all_points(pb, level=0):
+    m, d = pb.meshes[level], pb.dofs[level]
+    pts = [m.X]
+    if d.k == 2:
+        pts.append(0.5 * (m.X[m.edges[:, 0]] + m.X[m.edges[:, 1]]))
+        pts.append(np.array([m.X[f].mean(axis=0) for f in m.faces]))
+        pts.append(np.asarray(m.cell_centroid))
+    return np.concatenate(pts)
+
+
+def describe(pb, canonical_cubes=True):
     L = len(pb.meshes)
     levels = []
     for l in range(L):
@@ -33,12 +74,14 @@ def describe(pb):
         levels.append(lv)
     ke_ptr, ke_val, vptr, vert, be_ptr, be_val = [0], [], [0], [], [0], []
     vc_ptr, vc_val, geom = [0], [], []
-    for gd, verts, em, g in pb.asm.cells:
+    kblocks = [em["K"] for _, _, em, _ in pb.asm.cells]
+    if canonical_cubes:
+        kblocks = _canonical_cube_blocks(pb, kblocks)
+    for (gd, verts, em, g), K in zip(pb.asm.cells, kblocks):
         blk = np.concatenate([em["Pi1s"].ravel(), em["CPis"].ravel(), em["M1"].ravel()])
         vc_val.append(blk)
         vc_ptr.append(vc_ptr[-1] + blk.size)
         geom.append([g.xc[0], g.xc[1], g.xc[2], g.hc, g.volume])
-        K = em["K"]
         ke_val.append(K.ravel())
         ke_ptr.append(ke_ptr[-1] + K.size)
         vert.extend(verts.tolist())
@@ -47,6 +90,7 @@ def describe(pb):
         be_val.append(Bm.ravel())
         be_ptr.append(be_ptr[-1] + Bm.size)
     comp = np.full(pb.dofs[0].n_free, -1, dtype=np.int32)
+    lat, lat_n = dof_lattice(pb)
     for c, idx in enumerate(pb.null.floating):
         comp[idx] = c
     return {
@@ -59,4 +103,22 @@ def describe(pb):
         "vc_off": np.array(vc_ptr[:-1], dtype=np.int64), "vc_val": np.concatenate(vc_val),
         "cell_geom": np.array(geom, dtype=np.float64).ravel(),
         "vert_xyz": np.ascontiguousarray(pb.vertices, dtype=np.float64).ravel(),
+        "dof_lattice": lat, "lattice_n": lat_n,
     }
+
+
+def dof_points(pb, level=0):
+    """Support points of a level's free DOFs: vertices, edge midpoints, face
+    vertex means and cell centroids."""
+    return _all_points(pb, level)[pb.dofs[level].free_ids]
+
+
+def dof_lattice(pb):
+    """Integer lattice coordinates of the level-0 DOFs (-1 off the lattice):
+    the half-lattice of spacing h/2 for k = 2, the vertex lattice for k = 1."""
+    scale = 2 * pb.w.N if pb.k == 2 else pb.w.N
+    q = dof_points(pb) * scale
+    r = np.rint(q)
+    on = np.all(np.abs(q - r) < 1e-7, axis=1) & np.all((r >= 0) & (r <= scale), axis=1)
+    lat = np.where(on[:, None], r, -1).astype(np.int32)
+    return lat.ravel(), int(scale + 1)

@@ -37,7 +37,7 @@ def hier_for(request, name):
     if name not in _H:
         pb = request.getfixturevalue(name)
         print(f"[gpu velocity] building hierarchy for {name}", flush=True)
-        _H[name] = (fvem.Hierarchy(describe(pb)), pb)
+        _H[name] = (fvem.Hierarchy(describe(pb), lattice_min_fraction=1e-6), pb)
     return _H[name]
 
 

@@ -150,6 +150,13 @@ typedef struct {
     double lattice_min_fraction; /* with dof_lattice: use the lattice stencil layout on level 0
                                     when at least this fraction of its rows are stencil rows
                                     [0.5]; < 0: never */
+    int32_t column_codes;       /* 0: 16-bit column codes for every slice whose columns allow
+                                   them [default]; < 0: int32 columns everywhere */
+    int32_t galerkin_general;   /* nonzero: form every coarse operator as P^T A P by sparse
+                                   products on the host, for prolongations whose rows reach
+                                   beyond one coarse cell (the naive prolongation of Sec. 4);
+                                   0: the element-wise product, which requires the
+                                   diffusion-free structure [0] */
 } fvem_options;
 
 typedef enum { FVEM_PREC_FP64 = 0, FVEM_PREC_MIXED = 1 } fvem_precision;
@@ -174,6 +181,9 @@ typedef struct {
     int32_t n_levels;
     double ms_vcycle;       /* with profile: summed device time of the preconditioner's V-cycles */
     int32_t n_vcycle;       /* with profile: number of those V-cycles */
+    double ms_fine_stencil; /* with profile: summed device time of the lattice stencil launches
+                               inside the finest-level Chebyshev steps (0 without stencil rows) */
+    int32_t n_fine_stencil; /* with profile: number of those launches */
 } fvem_solve_stats;
 
 typedef struct fvem_hierarchy fvem_hierarchy;
@@ -281,6 +291,20 @@ fvem_status fvem_hierarchy_info(fvem_hierarchy *h, int32_t *n_levels, int64_t *n
 fvem_status fvem_level_storage(fvem_hierarchy *h, int32_t level, int64_t *nnz, int64_t *nnz_explicit,
                                int64_t *rows_templated, int32_t *n_templates, int32_t *template_width);
 
+/* Device memory the handle holds, by structure: bytes[0] level operators
+ * (sliced storage, templates, stencil tables), [1] transfers P_l and R_l,
+ * [2] level vectors and inverse diagonals, [3] divergence B and B^T, [4]
+ * velocity operators, [5] coarsest inverse, [6] CG workspace and the rest
+ * allocated after the coarsest factorisation, [7] the total (bytes needs 8
+ * entries). */
+fvem_status fvem_memory_breakdown(fvem_hierarchy *h, int64_t *bytes);
+
+/* Slices of level l's sliced operator by storage kind (FP32 value set):
+ * with 16-bit column codes, with int32 columns, whose rows all read value
+ * templates, and that store values. */
+fvem_status fvem_level_slices(fvem_hierarchy *h, int32_t level, int64_t *coded, int64_t *plain,
+                              int64_t *templated, int64_t *stored);
+
 /* Matrix bytes one application of A_l reads in the given precision
  * (fvem_precision: FP64 or MIXED = FP32 values): 2 bytes per nonzero of
  * slices with 16-bit column codes plus 256 per block table, 4 per nonzero
@@ -335,6 +359,17 @@ typedef struct fvem_grid fvem_grid;
 
 fvem_status fvem_grid_build(const double *V, int64_t nv, const int32_t *F, int64_t nt, int32_t N, int32_t k,
                             int32_t levels, int32_t dirichlet_top, int64_t coarse_max, fvem_grid **out);
+
+/* fvem_grid_build with flags: FVEM_GRID_NAIVE_PROLONGATION builds the naive
+ * VEM prolongation of Sec. 4 (shared DOFs copy, every other fine DOF takes
+ * the DOF functional of the coarse cell projection, averaged over the coarse
+ * cells holding it) instead of the diffusion-free one; its rows reach DOFs
+ * of neighbouring coarse cells, so a hierarchy built from it needs the
+ * galerkin_general option.  For the ablation of Sec. 4. */
+#define FVEM_GRID_NAIVE_PROLONGATION 0x1
+fvem_status fvem_grid_build_ex(const double *V, int64_t nv, const int32_t *F, int64_t nt, int32_t N, int32_t k,
+                               int32_t levels, int32_t dirichlet_top, int64_t coarse_max, int32_t flags,
+                               fvem_grid **out);
 
 /* Fills *d with pointers into the grid's own storage (valid until
  * fvem_grid_destroy); the result can be passed to fvem_hierarchy_build. */

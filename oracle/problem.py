@@ -25,7 +25,7 @@ def _dof_count(k):
 
 
 class Problem:
-    def __init__(self, workload, coarse_max=16384, max_levels=12, with_velocity=True):
+    def __init__(self, workload, coarse_max=16384, max_levels=12, with_velocity=True, naive_prolongation=False):
         w = workload
         self.w = w
         self.k = w.k
@@ -43,7 +43,8 @@ class Problem:
         self.host_kind = []
         for t in range(len(self.meshes) - 1):
             P, hk, P_raw = build_prolongation(self.meshes[t], self.dofs[t], self.meshes[t + 1],
-                                              self.dofs[t + 1], self.parents[t], return_raw=True)
+                                              self.dofs[t + 1], self.parents[t], return_raw=True,
+                                              naive=naive_prolongation)
             # Reading of this build (not a statement of the paper): a coarse
             # DOF whose prolongation column is zero carries no information
             # and is removed.  Sec. 5.2 argues that nestedness keeps the

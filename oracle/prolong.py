@@ -82,11 +82,45 @@ class CoarseLevel:
         return self._face[f]
 
 
-def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent, return_raw=False):
+class _CellContainment:
+    """Coarse cells whose closure holds a point or a fine face (naive prolongation)."""
+
+    def __init__(self, mesh):
+        self.mesh = mesh
+        self.planes = []
+        for c in range(len(mesh.cell_faces)):
+            pl = []
+            for f, o in mesh.cell_faces[c]:
+                n = mesh.face_normal[f] * o
+                pl.append((n, float(n @ mesh.X[mesh.faces[f][0]])))
+            self.planes.append(pl)
+        self.vert_cells = {}
+        for c in range(len(mesh.cell_faces)):
+            for v in mesh.cell_verts[c]:
+                self.vert_cells.setdefault(int(v), []).append(c)
+
+    def cells_holding(self, pts, E, tol=TOL):
+        """Cells (E first, then increasing id) whose closure holds every point of pts."""
+        cand = sorted({c for v in self.mesh.cell_verts[E] for c in self.vert_cells[int(v)]} - {E})
+        out = [E]
+        for c in cand:
+            if all(float(n @ p) <= d + tol for n, d in self.planes[c] for p in pts):
+                out.append(c)
+        return out
+
+
+def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent, return_raw=False, naive=False):
     """P [fine free x coarse free] as scipy CSR, plus the host kind per fine DOF.
 
     With ``return_raw`` also the prolongation before rounding-level weights
-    are dropped (every coarse column kept).
+    are dropped (every coarse column kept).  With ``naive`` the naive VEM
+    prolongation of Sec. 4 instead: DOFs shared with the coarse level (same
+    vertex, edge, face or cell) copy it, and every other fine DOF takes the
+    DOF functional of the coarse cell projection Pi_k; a DOF on the boundary
+    of several coarse cells takes the mean of their projections (the
+    reading for a face or edge shared by coarse cells, which the paper
+    leaves open).  Rows then reach DOFs of neighbouring coarse cells, the
+    connectivity diffusion the diffusion-free operator avoids.
     """
     k = fine_dofs.k
     CL = coarse_level = CoarseLevel(coarse_mesh, coarse_dofs)
@@ -94,6 +128,48 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent, r
     nvf, nef, nff = fine_dofs.nv, fine_dofs.ne, fine_dofs.nf
     rows = {}
     host_kind = np.full(fine_dofs.n, -1, dtype=np.int8)
+    cont = _CellContainment(coarse_mesh) if naive else None
+
+    def mean_rows(parts):
+        out = {}
+        for row in parts:
+            for j, w in row.items():
+                out[j] = out.get(j, 0.0) + w / len(parts)
+        return out
+
+    def naive_point_row(p, E):
+        g, Pis, cd = CL.cell(E)
+        for v in g.verts:
+            if np.linalg.norm(Xc[v] - p) < POINT_TOL:
+                return {int(v): 1.0}, 0
+        if k == 2:
+            for e in g.edges:
+                a, b = coarse_mesh.edges[e]
+                if np.linalg.norm(0.5 * (Xc[a] + Xc[b]) - p) < POINT_TOL:
+                    return {int(coarse_dofs.nv + e): 1.0}, 1
+        parts = []
+        for c in cont.cells_holding([p], E):
+            gc, Pc, cdc = CL.cell(c)
+            parts.append(dict(zip(cdc.tolist(), (gc.basis.mono(p, k)[0] @ Pc).tolist())))
+        return mean_rows(parts), 3
+
+    def naive_face_mean_row(fpts, E):
+        g, Pis, cd = CL.cell(E)
+        qp, qw = polygon_rule(fpts)
+        area_f = qw.sum()
+        fc = qw @ qp / area_f
+        for f in g.face_ids:
+            P = Xc[coarse_mesh.faces[f]]
+            n = coarse_mesh.face_normal[f]
+            qpc, qwc = polygon_rule(P)
+            if np.abs((fpts - P[0]) @ n).max() <= TOL and abs(qwc.sum() - area_f) < 1e-12 * area_f and \
+                    np.linalg.norm(qwc @ qpc / qwc.sum() - fc) < TOL:
+                return {int(coarse_dofs.nv + coarse_dofs.ne + f): 1.0}, 4
+        parts = []
+        for c in cont.cells_holding(fpts, E):
+            gc, Pc, cdc = CL.cell(c)
+            parts.append(dict(zip(cdc.tolist(), ((qw @ gc.basis.mono(qp, k) / area_f) @ Pc).tolist())))
+        return mean_rows(parts), 3
 
     def point_row(p, E):
         g, Pis, cd = CL.cell(E)
@@ -165,6 +241,8 @@ def build_prolongation(fine_mesh, fine_dofs, coarse_mesh, coarse_dofs, parent, r
         w = (qw @ g.basis.mono(qp, k) / qw.sum()) @ Pis
         return dict(zip(cd.tolist(), w.tolist())), 3
 
+    if naive:
+        point_row, face_mean_row = naive_point_row, naive_face_mean_row
     for c in range(len(fine_mesh.cell_faces)):
         E = int(parent[c])
         fd = fine_dofs.cell_dofs(c)

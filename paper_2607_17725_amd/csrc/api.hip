@@ -98,6 +98,7 @@ struct DevSELL {
   uint16_t *c16 = nullptr;
   int64_t n_ci = 0, n_c16 = 0;
   int64_t col_bytes = 0;            // algorithmic column bytes: 2 or 4 per nonzero, 256 per block table
+  int64_t slices_coded = 0, slices_plain = 0, slices_templated = 0, slices_stored = 0;
   DevValues d64, d32;               // exact FP64 and single-precision value sets
   double *v64 = nullptr, *tv64 = nullptr;
   float *v32 = nullptr, *tv32 = nullptr;
@@ -115,16 +116,20 @@ struct DevSELL {
     double *val64 = nullptr;
     float *val32 = nullptr;
     int32_t tn = 0, lat_n = 0;
+    bool standard = false;          // every class has the full order-2 support
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // set while the stencil launch is timed
     HostLattice host;               // tables, tiles and masks for read-back
   } st;
   DevSELLView<double> d() const {
     DevSELLView<double> v{n, m, nslices, sl, cp, ci, bt, c16, btab, d64.vp, v64, d64.tid, tv64, d64.tw, split, rowmap};
-    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val64};
+    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val64, st.standard,
+            st.ev0, st.ev1};
     return v;
   }
   DevSELLView<float> f() const {
     DevSELLView<float> v{n, m, nslices, sl, cp, ci, bt, c16, btab, d32.vp, v32, d32.tid, tv32, d32.tw, split, rowmap};
-    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val32};
+    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val32, st.standard,
+            st.ev0, st.ev1};
     return v;
   }
 };
@@ -161,6 +166,9 @@ struct fvem_hierarchy {
   int32_t *compc = nullptr;   // component of each DOF in the caller's order
   int ncomp0 = 0;
   double *scratch = nullptr;  // this device's copy of the static scratch array
+  // device bytes by structure: level operators, transfers, level vectors and
+  // diagonals, divergence, velocity operators, coarsest inverse, PCG workspace
+  int64_t mem_by_kind[7] = {0, 0, 0, 0, 0, 0, 0};
   // coarsest level
   int64_t nc = 0;
   double *G = nullptr;
@@ -174,6 +182,8 @@ struct fvem_hierarchy {
   size_t ev_used = 0;
   std::vector<hipEvent_t> evv;   // pairs around V-cycles
   size_t evv_used = 0;
+  std::vector<hipEvent_t> evs;   // pairs around the stencil launches of finest Chebyshev steps
+  size_t evs_used = 0;
   bool profiling = false;
 };
 
@@ -277,6 +287,10 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_template
     cast_f64_f32(static_cast<int64_t>(S.v32.tv.size()), tt, d.tv32, s);
     HIPCHECK(hipStreamSynchronize(s));   // before the temporaries and host arrays go
   }
+  for (int64_t k = 0; k < S.nslices; ++k) {
+    (S.bt[k] >= 0 ? d.slices_coded : d.slices_plain) += 1;
+    (S.v32.vp[k] < 0 ? d.slices_templated : d.slices_stored) += 1;
+  }
   d.hsp = std::move(S.sp);
   d.hcp = std::move(S.cp);
   d.hbt = std::move(S.bt);
@@ -294,7 +308,7 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_template
 // padded level order.  A is in the caller's order; inv maps caller DOF ->
 // level slot.
 static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, HostLattice &lat,
-                                 const std::vector<int32_t> &inv, int max_templates, hipStream_t s) {
+                                 const std::vector<int32_t> &inv, int max_templates, bool codes, hipStream_t s) {
   std::vector<int32_t> rest;   // caller DOFs of the sliced rows, in level order
   for (int64_t r = 0; r < static_cast<int64_t>(V.order.size()); ++r) {
     const int32_t i = V.order[r];
@@ -303,7 +317,7 @@ static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, 
   constexpr int64_t ORDER_WINDOW = 4096;
   const HostCSR R0 = permute(A, rest, &inv, V.n);
   const std::vector<int32_t> ord = window_order(R0, ORDER_WINDOW);
-  V.A = upload_sell(h, permute(R0, ord, nullptr, V.n), max_templates, true, s);
+  V.A = upload_sell(h, permute(R0, ord, nullptr, V.n), max_templates, codes, s);
   std::vector<int32_t> rowmap(ord.size());
   for (size_t k = 0; k < ord.size(); ++k) rowmap[k] = inv[rest[ord[k]]];
   V.A.rowmap = h->mem.upload(rowmap, s);
@@ -323,6 +337,18 @@ static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, 
   st.len = h->mem.upload(lens, s);
   st.off = h->mem.upload(lat.off, s);
   st.val64 = h->mem.upload(lat.val, s);
+  // the unrolled kernel applies when every class has the standard order-2
+  // support: offsets in [-2, 2] along even and [-1, 1] along odd coordinates
+  st.standard = true;
+  for (int t = 0; t < 8 && st.standard; ++t) {
+    const int ra = (t >> 2) ? 1 : 2, rb = ((t >> 1) & 1) ? 1 : 2, rc = (t & 1) ? 1 : 2;
+    int j = 0;
+    for (int da = -ra; da <= ra && st.standard; ++da)
+      for (int db = -rb; db <= rb && st.standard; ++db)
+        for (int dc = -rc; dc <= rc && st.standard; ++dc, ++j)
+          st.standard = j < lat.len[t] && lat.delta[128 * t + j] == (da + 2) * 25 + (db + 2) * 5 + (dc + 2);
+    st.standard = st.standard && j == lat.len[t];
+  }
   st.val32 = h->mem.alloc<float>(static_cast<int64_t>(lat.val.size()));
   cast_f64_f32(static_cast<int64_t>(lat.val.size()), st.val64, st.val32, s);
   HIPCHECK(hipStreamSynchronize(s));
@@ -487,6 +513,8 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 131072;
   const int max_templates = (o && o->max_templates != 0) ? o->max_templates : 4096;
   const double lattice_min = (o && o->lattice_min_fraction != 0) ? o->lattice_min_fraction : 0.5;
+  const bool general = o && o->galerkin_general != 0;
+  const bool codes = !(o && o->column_codes < 0);
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
   h->lv.resize(L);
@@ -552,6 +580,17 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   A[0] = assemble_blocks(h->n0, h->n0, c0, c0, ke);
   progress("hierarchy: level 0 assembled, n=%lld nnz=%lld", static_cast<long long>(A[0].n_rows),
            static_cast<long long>(A[0].rp.back()));
+  if (general) {
+    // prolongations that may reach beyond one coarse cell: A_{l+1} = P^T A_l P
+    // by sparse products on the host
+    for (int l = 0; l + 1 < L; ++l) {
+      P[l] = csr_of(g->levels[l].P, g->levels[l].n_dof, g->levels[l + 1].n_dof, "prolongation");
+      A[l + 1] = galerkin_product(A[l], P[l]);
+      progress("hierarchy: sparse Galerkin level %d, n=%lld nnz=%lld", l + 1,
+               static_cast<long long>(A[l + 1].n_rows), static_cast<long long>(A[l + 1].nnz()));
+    }
+    HostBlocks().val.swap(ke.val);
+  }
   // element-wise Galerkin products on the device; the coarse blocks stay
   // resident as the next level's fine blocks
   auto kmem = std::make_unique<DevMem>();
@@ -559,7 +598,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const double *kf = kmem->upload(ke.val, s);
   HIPCHECK(hipStreamSynchronize(s));
   { HostBlocks().val.swap(ke.val); }
-  for (int l = 0; l + 1 < L; ++l) {
+  for (int l = 0; l + 1 < L && !general; ++l) {
     const int64_t nf = g->levels[l].n_dof, nc = g->levels[l + 1].n_dof;
     P[l] = csr_of(g->levels[l].P, nf, nc, "prolongation");
     const HostCells &F = cells[l], &C = cells[l + 1];
@@ -682,9 +721,10 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   for (int l = 0; l < L; ++l) {
     Level &V = h->lv[l];
     std::vector<double> dinv;
+    int64_t mark = h->mem.bytes;
     if (l == 0 && lattice) {
       V.n = h->nl0;
-      upload_lattice_level(h, V, A[0], lat0, inv[0], max_templates, s);
+      upload_lattice_level(h, V, A[0], lat0, inv[0], max_templates, codes, s);
       dinv.assign(V.n, 0.0);
 #pragma omp parallel for schedule(dynamic, 4096)
       for (int64_t r = 0; r < V.n; ++r) {
@@ -698,7 +738,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     } else {
       V.n = A[l].n_rows;
       const bool split = small_rows >= 0 && V.n <= small_rows;
-      V.A = upload_sell(h, A[l], max_templates, true, s);
+      V.A = upload_sell(h, A[l], max_templates, codes, s);
       V.A.split = split;
       dinv.assign(V.n, 0.0);
       for (int64_t i = 0; i < V.n; ++i) {
@@ -708,18 +748,22 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
         dinv[i] = d > 0.0 ? 1.0 / d : 0.0;
       }
     }
+    h->mem_by_kind[0] += h->mem.bytes - mark;
+    mark = h->mem.bytes;
     V.dinv64 = h->mem.upload(dinv, s);
     V.dinv32 = h->mem.alloc<float>(V.n);
     cast_f64_f32(V.n, V.dinv64, V.dinv32, s);
     V.lmax = gershgorin_scaled(A[l]);
     cheb_coefficients(V, deg, lower);
+    h->mem_by_kind[2] += h->mem.bytes - mark;
+    mark = h->mem.bytes;
     if (l + 1 < L) {
       // transfers: rows sorted by length inside windows (own order), values
       // from templates where rows repeat; outputs are scattered back by rowmap
       auto transfer = [&](const HostCSR &T) {
         const std::vector<int32_t> ord = window_order(T, ORDER_WINDOW);
         const bool split = small_rows >= 0 && T.n_rows <= small_rows;
-        DevSELL d = upload_sell(h, permute(T, ord, nullptr), max_templates, true, s);
+        DevSELL d = upload_sell(h, permute(T, ord, nullptr), max_templates, codes, s);
         d.rowmap = h->mem.upload(ord, s);
         d.split = split;
         HIPCHECK(hipStreamSynchronize(s));
@@ -728,6 +772,8 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
       V.P = transfer(P[l]);
       V.R = transfer(transpose(P[l]));
     }
+    h->mem_by_kind[1] += h->mem.bytes - mark;
+    mark = h->mem.bytes;
     progress("hierarchy: level %d stored (%lld of %lld rows templated)", l,
              static_cast<long long>(V.A.d32.rows_templated), static_cast<long long>(V.n));
     // level vectors start at zero: lattice holes are never written and stay zero
@@ -741,17 +787,24 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     V.xb32 = h->mem.alloc_zero<float>(V.n, s);
     V.d32 = h->mem.alloc_zero<float>(V.n, s);
     V.r32 = h->mem.alloc_zero<float>(V.n, s);
+    h->mem_by_kind[2] += h->mem.bytes - mark;
     if (l + 1 < L) A[l] = HostCSR();   // the coarsest stays for the dense factorisation
   }
   if (g->n_vert > 0) {
+    const int64_t mark = h->mem.bytes;
     h->B = upload_csr(h, Bh, false, s);
     h->BT = upload_csr(h, transpose(Bh), false, s);
+    h->mem_by_kind[3] += h->mem.bytes - mark;
     progress("hierarchy: divergence stored");
   }
   h->comp0 = h->mem.upload(comp0, s);
   h->compc = h->mem.upload(comp_caller, s);
   h->scratch = static_scratch_address(h->device);
-  if (g->vc_off) build_velocity(h, g, c0, inv[0], s);
+  if (g->vc_off) {
+    const int64_t mark = h->mem.bytes;
+    build_velocity(h, g, c0, inv[0], s);
+    h->mem_by_kind[4] += h->mem.bytes - mark;
+  }
   progress("hierarchy: operators uploaded");
 
   // coarsest level: dense semi-definite factorisation and generalised inverse
@@ -788,6 +841,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     potrf_semidefinite(D, n, dg, rcond, flag, s);
     trinv_semidefinite(D, X, n, s);
     h->G = h->mem.alloc<double>(n * n);
+    h->mem_by_kind[5] += static_cast<int64_t>(sizeof(double)) * n * n;
     // G = X^T X
     gemm_f64(n, n, n, 1.0, X, n, 1, X, 1, n, 0.0, h->G, n, false, s);
     int hflag = 0;
@@ -800,6 +854,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   }
   // PCG workspace (level-0 vector length, zero holes)
   const int64_t n = h->nl0;
+  const int64_t mark_pcg = h->mem.bytes;
   h->b = h->mem.alloc_zero<double>(n, s);
   h->x = h->mem.alloc_zero<double>(n, s);
   h->r = h->mem.alloc_zero<double>(n, s);
@@ -812,6 +867,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   h->mean = h->mem.alloc<double>(MAX_COMP);
   h->lam = h->mem.alloc_zero<double>(n, s);
   HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&h->host), 8 * sizeof(double), hipHostMallocDefault));
+  h->mem_by_kind[6] += h->mem.bytes - mark_pcg;
   HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -880,10 +936,25 @@ static void smooth(fvem_hierarchy *h, int l, bool from_zero, hipStream_t s) {
   }
   for (int j = j0; j < deg; ++j) {
     const bool prof = h->profiling && l == 0;
-    if (prof) ev_record(h, s);
+    if (prof) {
+      ev_record(h, s);
+      if (L.A.st.ntiles > 0) {
+        // the stencil launch inside the step is timed on its own
+        while (h->evs.size() < h->evs_used + 2) {
+          hipEvent_t e;
+          HIPCHECK(hipEventCreate(&e));
+          h->evs.push_back(e);
+        }
+        L.A.st.ev0 = h->evs[h->evs_used++];
+        L.A.st.ev1 = h->evs[h->evs_used++];
+      }
+    }
     cheb_step<T>(V::A(L), V::b(L), V::dinv(L), V::x(L), V::d(L), V::xb(L), static_cast<T>(L.ca[j]),
                  static_cast<T>(L.cb[j]), s);
-    if (prof) ev_record(h, s);
+    if (prof) {
+      ev_record(h, s);
+      L.A.st.ev0 = L.A.st.ev1 = nullptr;
+    }
     std::swap(V::x(L), V::xb(L));
   }
 }
@@ -1033,6 +1104,7 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
   h->profiling = so && so->profile;
   h->ev_used = 0;
   h->evv_used = 0;
+  h->evs_used = 0;
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
@@ -1078,6 +1150,13 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
       float t = 0.f;
       HIPCHECK(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
       st->ms_fine_smoother += t;
+    }
+    st->ms_fine_stencil = 0.0;
+    st->n_fine_stencil = static_cast<int32_t>(h->evs_used / 2);
+    for (size_t k = 0; k + 1 < h->evs_used; k += 2) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, h->evs[k], h->evs[k + 1]));
+      st->ms_fine_stencil += t;
     }
     st->ms_vcycle = 0.0;
     st->n_vcycle = static_cast<int32_t>(h->evv_used / 2);
@@ -1308,6 +1387,30 @@ fvem_status fvem_vcycle_bytes(fvem_hierarchy *h, int32_t precision, int64_t *byt
   return FVEM_OK;
 }
 
+fvem_status fvem_memory_breakdown(fvem_hierarchy *h, int64_t *bytes) {
+  if (!h || !bytes) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  for (int k = 0; k < 7; ++k) bytes[k] = h->mem_by_kind[k];
+  bytes[7] = h->mem.bytes;
+  return FVEM_OK;
+}
+
+fvem_status fvem_level_slices(fvem_hierarchy *h, int32_t level, int64_t *coded, int64_t *plain,
+                              int64_t *templated, int64_t *stored) {
+  if (!h || level < 0 || level >= h->nlev) {
+    g_last_error = "bad handle or level";
+    return FVEM_ERR_INVALID;
+  }
+  const DevSELL &A = h->lv[level].A;
+  if (coded) *coded = A.slices_coded;
+  if (plain) *plain = A.slices_plain;
+  if (templated) *templated = A.slices_templated;
+  if (stored) *stored = A.slices_stored;
+  return FVEM_OK;
+}
+
 fvem_status fvem_level_stencil(fvem_hierarchy *h, int32_t level, int64_t *rows, int64_t *nnz, int64_t *tiles) {
   if (!h || level < 0 || level >= h->nlev) {
     g_last_error = "bad handle or level";
@@ -1533,6 +1636,7 @@ void fvem_hierarchy_destroy(fvem_hierarchy *h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->evv) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->evs) (void)hipEventDestroy(e);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
 }
@@ -1553,6 +1657,12 @@ extern "C" {
 
 fvem_status fvem_grid_build(const double *V, int64_t nv, const int32_t *F, int64_t nt, int32_t N, int32_t k,
                             int32_t levels, int32_t dirichlet_top, int64_t coarse_max, fvem_grid **out) {
+  return fvem_grid_build_ex(V, nv, F, nt, N, k, levels, dirichlet_top, coarse_max, 0, out);
+}
+
+fvem_status fvem_grid_build_ex(const double *V, int64_t nv, const int32_t *F, int64_t nt, int32_t N, int32_t k,
+                               int32_t levels, int32_t dirichlet_top, int64_t coarse_max, int32_t flags,
+                               fvem_grid **out) {
   if (!out) {
     g_last_error = "null output handle";
     return FVEM_ERR_INVALID;
@@ -1576,6 +1686,8 @@ fvem_status fvem_grid_build(const double *V, int64_t nv, const int32_t *F, int64
     in.L = levels;
     in.dirichlet = dirichlet_top != 0;
     in.coarse_max = coarse_max > 0 ? coarse_max : 16384;
+    check((flags & ~FVEM_GRID_NAIVE_PROLONGATION) == 0, "unknown grid flag");
+    in.naive = (flags & FVEM_GRID_NAIVE_PROLONGATION) != 0;
     try {
       grid::build_grid(in, &g->out);
     } catch (const std::runtime_error &e) {

@@ -9,11 +9,18 @@
 
 namespace fvem {
 
+// Each epilogue can also be split in two for kernels that overlap the
+// row's own vector reads with their gathers: pre(i) issues the reads,
+// apply(i, a, pre, x_i) finishes the row given x_i (x at the row itself).
+
 template <typename T>
 struct EpiStore {
   using acc_t = T;
   T *y;
   __device__ void operator()(int64_t i, T a) const { y[i] = a; }
+  struct Pre {};
+  __device__ Pre pre(int64_t) const { return {}; }
+  __device__ void apply(int64_t i, T a, const Pre &, T) const { y[i] = a; }
 };
 
 template <typename T>
@@ -22,6 +29,9 @@ struct EpiResidual {  // y = b - A x
   const T *b;
   T *y;
   __device__ void operator()(int64_t i, T a) const { y[i] = b[i] - a; }
+  struct Pre { T b; };
+  __device__ Pre pre(int64_t i) const { return {b[i]}; }
+  __device__ void apply(int64_t i, T a, const Pre &p, T) const { y[i] = p.b - a; }
 };
 
 template <typename T>
@@ -29,6 +39,9 @@ struct EpiAdd {  // y += A x  (prolong-and-correct)
   using acc_t = T;
   T *y;
   __device__ void operator()(int64_t i, T a) const { y[i] += a; }
+  struct Pre { T y; };
+  __device__ Pre pre(int64_t i) const { return {y[i]}; }
+  __device__ void apply(int64_t i, T a, const Pre &p, T) const { y[i] = p.y + a; }
 };
 
 struct EpiScaled {  // y = alpha A x
@@ -48,6 +61,13 @@ struct EpiCheb {  // d = ca d + cb dinv (b - A xin);  xout = xin + d
     const T dn = ca * d[i] + cb * dinv[i] * (b[i] - a);
     d[i] = dn;
     xout[i] = xin[i] + dn;
+  }
+  struct Pre { T b, dinv, d; };
+  __device__ Pre pre(int64_t i) const { return {b[i], dinv[i], d[i]}; }
+  __device__ void apply(int64_t i, T a, const Pre &p, T x) const {
+    const T dn = ca * p.d + cb * p.dinv * (p.b - a);
+    d[i] = dn;
+    xout[i] = x + dn;
   }
 };
 

@@ -30,6 +30,7 @@
 #include <cstring>
 #include <numeric>
 #include <omp.h>
+#include <functional>
 #include <queue>
 #include <stdexcept>
 #include <unordered_map>
@@ -124,6 +125,7 @@ struct BuilderImpl {
   bool dirichlet;
   int64_t coarse_max;
   int max_levels;
+  bool naive = false;
   std::vector<V3> TV;
   std::vector<std::array<int32_t, 3>> TF;
   std::vector<V3> tn;
@@ -919,6 +921,56 @@ struct BuilderImpl {
         if (owner[r] < 0) owner[r] = static_cast<int32_t>(c);
     std::vector<Row> rows(nrf);
     constexpr double tol = 1e-9;
+    // naive prolongation: coarse cells around each vertex, and whether a
+    // point lies in a coarse cell's closure
+    std::vector<std::vector<int32_t>> vcells;
+    if (naive) {
+      vcells.resize(Mc.nv());
+      for (int64_t c = 0; c < ncc; ++c)
+        for (int64_t q = Mc.cvptr[c]; q < Mc.cvptr[c + 1]; ++q) vcells[Mc.cvert[q]].push_back(static_cast<int32_t>(c));
+    }
+    auto in_cell = [&](int64_t c, V3 p) {
+      for (int64_t q = Mc.cfptr[c]; q < Mc.cfptr[c + 1]; ++q) {
+        const int32_t f = Mc.cface[q];
+        const V3 n = static_cast<double>(Mc.corient[q]) * Mc.fnormal[f];
+        if (dot(n, p - Mc.X[Mc.fvert[Mc.fptr[f]]]) > tol) return false;
+      }
+      return true;
+    };
+    // coarse cells (E first, then increasing id) whose closure holds all points
+    auto cells_holding = [&](int32_t E, const std::vector<V3> &pts) {
+      std::vector<int32_t> cand;
+      for (int64_t q = Mc.cvptr[E]; q < Mc.cvptr[E + 1]; ++q)
+        for (int32_t c : vcells[Mc.cvert[q]])
+          if (c != E) cand.push_back(c);
+      std::sort(cand.begin(), cand.end());
+      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      std::vector<int32_t> out{E};
+      for (int32_t c : cand) {
+        bool all = true;
+        for (const V3 &p : pts) all = all && in_cell(c, p);
+        if (all) out.push_back(c);
+      }
+      return out;
+    };
+    // the mean over cells of their projection's functional (mvals_of gives
+    // the monomial values of the functional in cell c's basis)
+    auto mean_cell_rows = [&](const std::vector<int32_t> &cells, const std::function<void(int32_t, double *)> &mvals_of,
+                              Row &R) {
+      const int Nk = vem::npoly3(k);
+      const double wgt = 1.0 / static_cast<double>(cells.size());
+      for (int32_t c : cells) {
+        double mv[10];
+        mvals_of(c, mv);
+        const std::vector<int32_t> craw = cell_raw_dofs(Mc, c);
+        const int nE = static_cast<int>(craw.size());
+        for (int r = 0; r < nE; ++r) {
+          double sum = 0;
+          for (int a = 0; a < Nk; ++a) sum += mv[a] * cproj[c].Pis[a * nE + r];
+          if (sum != 0.0) R.e.push_back({craw[r], wgt * sum});
+        }
+      }
+    };
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t c = 0; c < Mf.nc(); ++c) {
       const int32_t E = par[c];
@@ -991,13 +1043,33 @@ struct BuilderImpl {
         pj.basis.eval(p, k, mv);
         cell_row(mv, R);
       };
+      // naive prolongation of a point: shared vertex or edge-midpoint DOFs
+      // copy, any other point takes the mean of the projections of the
+      // coarse cells holding it
+      auto naive_point_row = [&](V3 p, Row &R) {
+        for (int64_t q = Mc.cvptr[E]; q < Mc.cvptr[E + 1]; ++q)
+          if (norm(Mc.X[Mc.cvert[q]] - p) < kVertTol) {
+            R.e.push_back({Mc.cvert[q], 1.0});
+            return;
+          }
+        if (k == 2)
+          for (int64_t q = Mc.ceptr[E]; q < Mc.ceptr[E + 1]; ++q) {
+            const int32_t e = Mc.cedge[q];
+            if (norm(0.5 * (Mc.X[Mc.edges[e][0]] + Mc.X[Mc.edges[e][1]]) - p) < kVertTol) {
+              R.e.push_back({static_cast<int32_t>(Mc.nv() + e), 1.0});
+              return;
+            }
+          }
+        mean_cell_rows(cells_holding(E, {p}), [&](int32_t cc2, double *mv) { cproj[cc2].basis.eval(p, k, mv); }, R);
+      };
       const std::vector<int32_t> fraw = cell_raw_dofs(Mf, c);
       for (int32_t r : fraw) {
         if (owner[r] != c) continue;
         Row &R = rows[r];
         const int kind = raw_kind(Mf, r);
         if (kind <= 1) {
-          point_row(raw_point(Mf, r), R);
+          if (naive) naive_point_row(raw_point(Mf, r), R);
+          else point_row(raw_point(Mf, r), R);
         } else if (kind == 2) {
           const int64_t f = r - Mf.nv() - Mf.ne();
           const std::vector<V3> P = face_points(Mf, static_cast<int32_t>(f), 1);
@@ -1034,6 +1106,12 @@ struct BuilderImpl {
               done = true;
               break;
             }
+          }
+          if (naive && !done) {
+            // the mean over the coarse cells holding the fine face of their
+            // projection's mean on it
+            mean_cell_rows(cells_holding(E, P), [&](int32_t cc2, double *mv) { vem::polygon_mean(P, cproj[cc2].basis, k, mv); }, R);
+            done = true;
           }
           for (size_t t = 0; t < coplanar.size() && !done; ++t) {
             const int32_t F2 = coplanar[t];
@@ -1370,6 +1448,7 @@ void build_grid(const Input &in, Output *out) {
   b.dirichlet = in.dirichlet;
   b.coarse_max = in.coarse_max;
   b.max_levels = in.max_levels;
+  b.naive = in.naive;
   b.out = out;
   b.TV.resize(in.nv);
   for (int64_t i = 0; i < in.nv; ++i) b.TV[i] = V3(in.V[3 * i], in.V[3 * i + 1], in.V[3 * i + 2]);

@@ -20,6 +20,7 @@ struct Input {
   bool dirichlet = false;      // p = 0 on z = 1
   int64_t coarse_max = 16384;  // keep coarsening while the coarsest level is larger
   int max_levels = 12;
+  bool naive = false;          // the naive prolongation of Sec. 4 (ablation) instead of the diffusion-free one
 };
 
 struct LevelOut {

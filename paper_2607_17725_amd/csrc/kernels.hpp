@@ -31,6 +31,8 @@ struct StencilView {
   const int32_t *len = nullptr;        // 8 entry counts
   const int32_t *off = nullptr;        // 8 x 128 LDS offsets
   const T *val = nullptr;              // 8 x 128 values
+  bool standard = false;               // every class has the full order-2 support (unrolled kernel)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;   // recorded around the stencil launch when set
 };
 
 // Sliced ELLPACK with 64-row slices (one wavefront lane per row).  Slice s

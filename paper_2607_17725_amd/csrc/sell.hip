@@ -128,13 +128,12 @@ __device__ __forceinline__ AT row_sum(int groups, const Cols &cols, const Vals &
 }
 
 template <typename VT, typename XT, class Epi>
-__global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(
-    int64_t n, int64_t nslices, const int32_t *__restrict__ sl, const int64_t *__restrict__ cpo,
+__device__ __forceinline__ void sell_block(
+    int64_t blk, int64_t n, int64_t nslices, const int32_t *__restrict__ sl, const int64_t *__restrict__ cpo,
     const int32_t *__restrict__ ci, const int64_t *__restrict__ bt, const uint16_t *__restrict__ c16,
     const int32_t *__restrict__ btab, const int64_t *__restrict__ vp, const VT *__restrict__ val,
     const int32_t *__restrict__ tid, const VT *__restrict__ tv, int32_t tw, const int32_t *__restrict__ rowmap,
-    const XT *__restrict__ x, Epi epi) {
-  const int64_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const XT *__restrict__ x, const Epi &epi) {
   const int64_t slice = blk * SELL_WAVES + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (slice >= nslices) return;   // whole wavefronts only: every lane below takes part in the cross-lane reads
@@ -155,6 +154,17 @@ __global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(
   }
   const int64_t row = slice * 64 + lane;
   if (row < n) epi(rowmap ? static_cast<int64_t>(rowmap[row]) : row, acc);
+}
+
+template <typename VT, typename XT, class Epi>
+__global__ __launch_bounds__(64 * SELL_WAVES) void sell_kernel(
+    int64_t n, int64_t nslices, const int32_t *__restrict__ sl, const int64_t *__restrict__ cpo,
+    const int32_t *__restrict__ ci, const int64_t *__restrict__ bt, const uint16_t *__restrict__ c16,
+    const int32_t *__restrict__ btab, const int64_t *__restrict__ vp, const VT *__restrict__ val,
+    const int32_t *__restrict__ tid, const VT *__restrict__ tv, int32_t tw, const int32_t *__restrict__ rowmap,
+    const XT *__restrict__ x, Epi epi) {
+  sell_block<VT, XT, Epi>(xcd_contiguous(blockIdx.x, gridDim.x), n, nslices, sl, cpo, ci, bt, c16, btab, vp, val,
+                          tid, tv, tw, rowmap, x, epi);
 }
 
 // Small levels (a few thousand slices) cannot fill 256 CUs with one
@@ -215,14 +225,61 @@ __global__ __launch_bounds__(256) void sell_split_kernel(
 // half-wavefront on distinct banks.  The class table (LDS offset, value) is
 // wave-uniform, so its entries come through scalar loads; every lane sums its
 // entries in the table's fixed order (deterministic).
+// Rows of class T = 4 ta + 2 tb + tc with the standard order-2 support:
+// offsets in [-2, 2] along even coordinates and [-1, 1] along odd ones, in
+// the table's order (increasing offset code).  Offsets and LDS addresses are
+// compile-time constants; the values come from the wave-uniform table.
+template <int T, typename VT, typename XT, typename AT>
+__device__ __forceinline__ AT stencil_row_std(const XT *hp, const VT *val) {
+  constexpr int ta = T >> 2, tb = (T >> 1) & 1, tc = T & 1;
+  constexpr int ra = ta ? 1 : 2, rb = tb ? 1 : 2, rc = tc ? 1 : 2;
+  AT acc = 0;
+  int j = 0;
+#pragma unroll
+  for (int da = -ra; da <= ra; ++da)
+#pragma unroll
+    for (int db = -rb; db <= rb; ++db)
+#pragma unroll
+      for (int dc = -rc; dc <= rc; ++dc) {
+        const int ua = (ta + da) & 1, ub = (tb + db) & 1, uc = (tc + dc) & 1;
+        const int off = (4 * ua + 2 * ub + uc) * STENCIL_SUB + ((ta + da + 2 - ua) / 2) * STENCIL_P1 +
+                        ((tb + db + 2 - ub) / 2) * STENCIL_P2 + (tc + dc + 2 - uc) / 2;
+        acc += static_cast<AT>(val[j]) * static_cast<AT>(hp[off]);
+        ++j;
+      }
+  return acc;
+}
+
+// One workgroup of 8 wavefronts per tile; wavefront t handles the 64 slots
+// of class t.  The tile's 8^3 points plus a 2-point halo (12^3 values) are
+// staged in LDS, split by class into 6^3 sub-grids.
 template <typename VT, typename XT, class Epi>
 __global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const XT *__restrict__ x, Epi epi) {
   __shared__ XT halo[8 * STENCIL_SUB];
+  __shared__ int32_t nbase[27];   // slot bases of the tile and its 26 neighbours (-1: none)
   const int64_t b = xcd_contiguous(blockIdx.x, gridDim.x);
   const int32_t tile = st.tiles[b];
   const int tn = st.tn, N = st.lat_n;
   const int Ta = tile / (tn * tn), Tb = (tile / tn) % tn, Tc = tile % tn;
-  for (int e = threadIdx.x; e < 1728; e += 512) {
+  if (threadIdx.x < 27) {
+    const int ua = Ta + static_cast<int>(threadIdx.x) / 9 - 1, ub = Tb + (static_cast<int>(threadIdx.x) / 3) % 3 - 1,
+              uc = Tc + static_cast<int>(threadIdx.x) % 3 - 1;
+    nbase[threadIdx.x] = (ua >= 0 && ua < tn && ub >= 0 && ub < tn && uc >= 0 && uc < tn)
+                             ? st.tile_base[(ua * tn + ub) * tn + uc] : -1;
+  }
+  __syncthreads();
+  // the row's own vector reads go out with the halo gathers
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const bool active = (st.mask[8 * b + t] >> lane) & 1;
+  const int64_t row = static_cast<int64_t>(nbase[13]) + 64 * t + lane;
+  typename Epi::Pre pre{};
+  if (active) pre = epi.pre(row);
+  // 1728 halo values, at most 4 per thread, issued before any is used
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 512 * q;
+    if (e >= 1728) break;
     const int tp = e / 216, r = e - 216 * tp;
     const int I = r / 36, J = (r / 6) % 6, K = r % 6;
     const int a = 8 * Ta - 2 + (tp >> 2) + 2 * I;
@@ -230,30 +287,45 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const 
     const int c = 8 * Tc - 2 + (tp & 1) + 2 * K;
     XT v = 0;
     if (a >= 0 && a < N && bb >= 0 && bb < N && c >= 0 && c < N) {
-      const int32_t base = st.tile_base[((a >> 3) * tn + (bb >> 3)) * tn + (c >> 3)];
+      const int32_t base = nbase[((a >> 3) - Ta + 1) * 9 + ((bb >> 3) - Tb + 1) * 3 + ((c >> 3) - Tc + 1)];
       if (base >= 0) v = x[base + 64 * tp + 16 * ((a & 7) >> 1) + 4 * ((bb & 7) >> 1) + ((c & 7) >> 1)];
     }
     halo[tp * STENCIL_SUB + I * STENCIL_P1 + J * STENCIL_P2 + K] = v;
   }
   __syncthreads();
-  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const uint64_t m = st.mask[8 * b + t];
-  if (!((m >> lane) & 1)) return;
+  if (!active) return;
   const XT *hp = halo + (lane >> 4) * STENCIL_P1 + ((lane >> 2) & 3) * STENCIL_P2 + (lane & 3);
-  const int len = st.len[t];
-  const int32_t *off = st.off + 128 * t;
   const VT *val = st.val + 128 * t;
   using AT = typename Epi::acc_t;
   AT acc = 0;
-  for (int j = 0; j < len; ++j) acc += static_cast<AT>(val[j]) * static_cast<AT>(hp[off[j]]);
-  epi(static_cast<int64_t>(st.tile_base[tile]) + 64 * t + lane, acc);
+  if (st.standard) {
+    switch (t) {
+      case 0: acc = stencil_row_std<0, VT, XT, AT>(hp, val); break;
+      case 1: acc = stencil_row_std<1, VT, XT, AT>(hp, val); break;
+      case 2: acc = stencil_row_std<2, VT, XT, AT>(hp, val); break;
+      case 3: acc = stencil_row_std<3, VT, XT, AT>(hp, val); break;
+      case 4: acc = stencil_row_std<4, VT, XT, AT>(hp, val); break;
+      case 5: acc = stencil_row_std<5, VT, XT, AT>(hp, val); break;
+      case 6: acc = stencil_row_std<6, VT, XT, AT>(hp, val); break;
+      default: acc = stencil_row_std<7, VT, XT, AT>(hp, val); break;
+    }
+  } else {
+    const int len = st.len[t];
+    const int32_t *off = st.off + 128 * t;
+    for (int j = 0; j < len; ++j) acc += static_cast<AT>(val[j]) * static_cast<AT>(hp[off[j]]);
+  }
+  // x at the row itself: class t's sub-grid, one point inside the halo along each axis
+  const XT xi = hp[t * STENCIL_SUB + STENCIL_P1 + STENCIL_P2 + 1];
+  epi.apply(row, acc, pre, static_cast<AT>(xi));
 }
 
 template <typename VT, typename XT, class Epi>
 static void launch_sell(const DevSELLView<VT> &A, const XT *x, Epi epi, hipStream_t s) {
-  if (A.st.ntiles > 0)
+  if (A.st.ntiles > 0) {
+    if (A.st.ev0) (void)hipEventRecord(A.st.ev0, s);
     stencil_kernel<VT, XT, Epi><<<static_cast<unsigned>(A.st.ntiles), 512, 0, s>>>(A.st, x, epi);
+    if (A.st.ev1) (void)hipEventRecord(A.st.ev1, s);
+  }
   if (A.nslices == 0) return;
   if (A.split) {
     const dim3 grid(static_cast<unsigned>((A.n * SELL_SPLIT + 255) / 256));

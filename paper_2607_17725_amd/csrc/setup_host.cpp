@@ -209,6 +209,54 @@ HostCSR transpose(const HostCSR &A) {
   return T;
 }
 
+HostCSR multiply(const HostCSR &X, const HostCSR &Y) {
+  HostCSR C;
+  C.n_rows = X.n_rows;
+  C.n_cols = Y.n_cols;
+  std::vector<std::vector<int32_t>> cols(X.n_rows);
+  std::vector<std::vector<double>> vals(X.n_rows);
+#pragma omp parallel
+  {
+    std::vector<double> acc(Y.n_cols, 0.0);
+    std::vector<int32_t> mark(Y.n_cols, -1), used;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t i = 0; i < X.n_rows; ++i) {
+      used.clear();
+      for (int64_t a = X.rp[i]; a < X.rp[i + 1]; ++a) {
+        const int32_t k = X.ci[a];
+        const double xv = X.v[a];
+        for (int64_t b = Y.rp[k]; b < Y.rp[k + 1]; ++b) {
+          const int32_t j = Y.ci[b];
+          if (mark[j] != i) {
+            mark[j] = static_cast<int32_t>(i);
+            acc[j] = 0.0;
+            used.push_back(j);
+          }
+          acc[j] += xv * Y.v[b];
+        }
+      }
+      std::sort(used.begin(), used.end());
+      cols[i] = used;
+      vals[i].resize(used.size());
+      for (size_t q = 0; q < used.size(); ++q) vals[i][q] = acc[used[q]];
+    }
+  }
+  C.rp.assign(C.n_rows + 1, 0);
+  for (int64_t i = 0; i < C.n_rows; ++i) C.rp[i + 1] = C.rp[i] + static_cast<int64_t>(cols[i].size());
+  C.ci.resize(C.rp[C.n_rows]);
+  C.v.resize(C.rp[C.n_rows]);
+  for (int64_t i = 0; i < C.n_rows; ++i) {
+    std::copy(cols[i].begin(), cols[i].end(), C.ci.begin() + C.rp[i]);
+    std::copy(vals[i].begin(), vals[i].end(), C.v.begin() + C.rp[i]);
+  }
+  return C;
+}
+
+HostCSR galerkin_product(const HostCSR &A, const HostCSR &P) {
+  const HostCSR AP = multiply(A, P);
+  return multiply(transpose(P), AP);
+}
+
 std::vector<int32_t> window_order(const HostCSR &A, int64_t w) {
   const int64_t n = A.n_rows;
   std::vector<int32_t> order(n);

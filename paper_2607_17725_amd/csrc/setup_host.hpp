@@ -55,6 +55,14 @@ HostBlocks galerkin_blocks(const HostCells &fine, const HostBlocks &kf, const in
 
 HostCSR transpose(const HostCSR &A);
 
+// C = X Y (sparse products, columns sorted; each entry sums its terms in
+// the order of X's row and then Y's rows, so the result is deterministic).
+HostCSR multiply(const HostCSR &X, const HostCSR &Y);
+
+// Galerkin operator A_c = P^T A P by sparse products, for prolongations
+// whose rows may reach beyond one coarse cell (no element-wise form).
+HostCSR galerkin_product(const HostCSR &A, const HostCSR &P);
+
 // Level order of the sliced storage: inside each window of w consecutive
 // rows (w a multiple of 64), rows by decreasing length (stable); then the
 // window's full 64-row chunks ordered by their smallest original row, so the

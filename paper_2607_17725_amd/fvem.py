@@ -17,6 +17,7 @@ STATUS = {0: "OK", 1: "INVALID", 2: "HIP", 3: "OOM", 4: "NOT_SPD", 5: "NOT_CONVE
 OP_K, OP_B, OP_BT, OP_VCYCLE, OP_VCYCLE32, OP_PROJECT = range(6)
 OP_PI1, OP_PI1T, OP_G, OP_GT, OP_MASS, OP_AV, OP_AVT = range(6, 13)
 APPLY_ACCUMULATE = 0x100
+GRID_NAIVE_PROLONGATION = 0x1
 PREC_FP64, PREC_MIXED = 0, 1
 INPUT_VELOCITY, INPUT_RHS = 0, 1
 
@@ -56,7 +57,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("cheb_degree", ctypes.c_int32), ("cheb_lower", ctypes.c_double),
                 ("coarse_dense_max", ctypes.c_int32), ("coarse_rcond", ctypes.c_double),
                 ("coarse_shift", ctypes.c_double), ("small_level_rows", ctypes.c_int64),
-                ("max_templates", ctypes.c_int32), ("lattice_min_fraction", ctypes.c_double)]
+                ("max_templates", ctypes.c_int32), ("lattice_min_fraction", ctypes.c_double),
+                ("column_codes", ctypes.c_int32), ("galerkin_general", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -67,7 +69,8 @@ class SolveOpts(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_fine_smoother", ctypes.c_double), ("n_fine_smoother", ctypes.c_int32),
-                ("n_levels", ctypes.c_int32), ("ms_vcycle", ctypes.c_double), ("n_vcycle", ctypes.c_int32)]
+                ("n_levels", ctypes.c_int32), ("ms_vcycle", ctypes.c_double), ("n_vcycle", ctypes.c_int32),
+                ("ms_fine_stencil", ctypes.c_double), ("n_fine_stencil", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -78,7 +81,8 @@ EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_app
            "fvem_grid_describe", "fvem_grid_info", "fvem_grid_level_points", "fvem_grid_destroy",
            "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells",
            "fvem_level_storage", "fvem_level_bytes", "fvem_project_noalloc", "fvem_level_stencil",
-           "fvem_transfer_storage", "fvem_vcycle_bytes"]
+           "fvem_transfer_storage", "fvem_vcycle_bytes", "fvem_level_slices",
+           "fvem_memory_breakdown", "fvem_grid_build_ex"]
 
 _lib = None
 
@@ -116,6 +120,10 @@ def load(path=LIB_PATH):
     lib.fvem_transfer_storage.argtypes = [vp, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(i64)]
     lib.fvem_transfer_storage.restype = ctypes.c_int
+    lib.fvem_memory_breakdown.argtypes = [vp, vp]
+    lib.fvem_memory_breakdown.restype = ctypes.c_int
+    lib.fvem_level_slices.argtypes = [vp, i32] + [ctypes.POINTER(i64)] * 4
+    lib.fvem_level_slices.restype = ctypes.c_int
     lib.fvem_vcycle_bytes.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.fvem_vcycle_bytes.restype = ctypes.c_int
     lib.fvem_level_stencil.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -133,6 +141,8 @@ def load(path=LIB_PATH):
     lib.fvem_last_error.restype = ctypes.c_char_p
     lib.fvem_grid_build.argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i64, ctypes.POINTER(vp)]
     lib.fvem_grid_build.restype = ctypes.c_int
+    lib.fvem_grid_build_ex.argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i64, i32, ctypes.POINTER(vp)]
+    lib.fvem_grid_build_ex.restype = ctypes.c_int
     lib.fvem_grid_describe.argtypes = [vp, ctypes.POINTER(_Grid)]
     lib.fvem_grid_describe.restype = ctypes.c_int
     lib.fvem_grid_info.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
@@ -172,7 +182,7 @@ class Hierarchy:
 
     def __init__(self, desc, stream=None, cheb_degree=5, cheb_lower=1.0 / 30.0, coarse_dense_max=16384,
                  coarse_rcond=0.0, coarse_shift=1e-8, small_level_rows=0, max_templates=0,
-                 lattice_min_fraction=0.0):
+                 lattice_min_fraction=0.0, galerkin_general=False, column_codes=0):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -181,7 +191,8 @@ class Hierarchy:
             g = _Grid()
             _check(lib.fvem_grid_describe(desc._g, ctypes.byref(g)))
             self._finish(lib, g, [desc], stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond,
-                         coarse_shift, small_level_rows, max_templates, lattice_min_fraction)
+                         coarse_shift, small_level_rows, max_templates, lattice_min_fraction, galerkin_general,
+                         column_codes)
             return
         keep = []
         L = len(desc["levels"])
@@ -223,13 +234,13 @@ class Hierarchy:
         g.n_components = int(desc.get("n_components", 0))
         g.lattice_n = int(desc.get("lattice_n", 0))
         self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                     small_level_rows, max_templates, lattice_min_fraction)
+                     small_level_rows, max_templates, lattice_min_fraction, galerkin_general, column_codes)
 
     def _finish(self, lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                small_level_rows, max_templates, lattice_min_fraction):
+                small_level_rows, max_templates, lattice_min_fraction, galerkin_general, column_codes):
         import torch
         opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift, small_level_rows,
-                        max_templates, lattice_min_fraction)
+                        max_templates, lattice_min_fraction, int(column_codes), 1 if galerkin_general else 0)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         _check(lib.fvem_hierarchy_build(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
@@ -360,6 +371,19 @@ class Hierarchy:
         return dict(zip(("nnz", "nnz_explicit", "rows_templated", "n_templates", "template_width"),
                         (x.value for x in v)))
 
+    def memory_breakdown(self):
+        """Device bytes held by the handle, by structure (fvem_memory_breakdown)."""
+        b = np.zeros(8, dtype=np.int64)
+        _check(load().fvem_memory_breakdown(self._h, b.ctypes.data))
+        return dict(zip(("level_operators", "transfers", "level_vectors", "divergence", "velocity_operators",
+                         "coarsest_inverse", "cg_workspace", "total"), (int(v) for v in b)))
+
+    def level_slices(self, level):
+        """Slices of level ``level``'s sliced operator: coded, plain, templated, stored."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(load().fvem_level_slices(self._h, level, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("coded", "plain", "templated", "stored"), (x.value for x in v)))
+
     def transfer_storage(self, level, precision=PREC_MIXED):
         """P_level nonzeros and the matrix bytes of one application of P_level and R_level."""
         v = [ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()]
@@ -409,13 +433,14 @@ class Hierarchy:
 class Grid:
     """Native cut-cell grid, VEM operators and hierarchy built from a boundary mesh (host C++)."""
 
-    def __init__(self, V, F, N, k, levels=5, dirichlet_top=False, coarse_max=16384):
+    def __init__(self, V, F, N, k, levels=5, dirichlet_top=False, coarse_max=16384, naive_prolongation=False):
         lib = load()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
         g = ctypes.c_void_p()
-        _check(lib.fvem_grid_build(V.ctypes.data, len(V), F.ctypes.data, len(F), int(N), int(k), int(levels),
-                                   1 if dirichlet_top else 0, int(coarse_max), ctypes.byref(g)))
+        _check(lib.fvem_grid_build_ex(V.ctypes.data, len(V), F.ctypes.data, len(F), int(N), int(k), int(levels),
+                                      1 if dirichlet_top else 0, int(coarse_max),
+                                      GRID_NAIVE_PROLONGATION if naive_prolongation else 0, ctypes.byref(g)))
         self._g = g
         self.N, self.k = N, k
         xv, nv, dp, dk = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_void_p(), ctypes.c_void_p()

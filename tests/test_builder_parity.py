@@ -185,3 +185,29 @@ def test_native_builder_matches_oracle(name):
         assert (comp < 0).all()
     else:
         assert desc["n_components"] == len(pb.null.floating)
+
+
+def test_native_naive_prolongation_matches_oracle():
+    """The builder's naive prolongation (Sec. 4 ablation) equals the oracle's, row by row."""
+    import synth
+    from paper_2607_17725_amd import fvem
+    pb = oracle_problem("c3", 8, naive_prolongation=True)
+    w = synth.get_config("c3", N=8)
+    V, F = w.mesh()
+    g = fvem.Grid(V, F, w.N, w.k, w.levels, w.dirichlet_top, naive_prolongation=True)
+    desc = g.describe()
+    L = len(pb.meshes)
+    assert len(desc["levels"]) == L
+    perms = []
+    for l in range(L):
+        d = pb.dofs[l]
+        assert desc["levels"][l]["n_dof"] == d.n_free, f"level {l}"
+        pts, knd = g.level_points(l)
+        perms.append(_match(pts, knd, d.point[d.free_ids], d.kind[d.free_ids]))
+    for l in range(L - 1):
+        rp, ci, va = desc["levels"][l]["P"]
+        nf, nc = desc["levels"][l]["n_dof"], desc["levels"][l + 1]["n_dof"]
+        Pn = sp.csr_matrix((va, ci, rp), shape=(nf, nc))
+        Qf = sp.csr_matrix((np.ones(nf), (perms[l], np.arange(nf))), shape=(nf, nf))
+        Qc = sp.csr_matrix((np.ones(nc), (perms[l + 1], np.arange(nc))), shape=(nc, nc))
+        assert _rel_rows(Qf @ Pn @ Qc.T, pb.P[l]) < 1e-10, f"P level {l}"

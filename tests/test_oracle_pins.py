@@ -227,3 +227,34 @@ def test_dropped_weights_below_sheet_rounding(c4_small):
         coo = P.tocoo()
         kept = np.abs(coo.data) > 1e-13 * rowmax[coo.row]
         assert pb.P[t].nnz == int(kept[used[coo.col]].sum())
+
+
+# ------------------------------------------------------------------ naive prolongation (ablation)
+
+def test_naive_prolongation_reproduces_and_diffuses():
+    """The naive prolongation of Sec. 4 reproduces quadratics like the
+    diffusion-free one, but its Galerkin operators couple DOFs of different
+    coarse cells and grow denser level by level (the paper's diffusion)."""
+    from conftest import oracle_problem
+    from test_oracle_global import _dof_values, _poly
+    pn = oracle_problem("c3", 8, naive_prolongation=True)
+    pd = oracle_problem("c3", 8)
+    q, _ = _poly(2, 5)
+    for t, P in enumerate(pn.P):
+        Dc, Df = _dof_values(pn, t + 1, q), _dof_values(pn, t, q)
+        assert np.abs(P @ Dc - Df).max() < 1e-11 * max(np.abs(Df).max(), 1.0)
+    An, Ad = pn.mg.A, pd.mg.A
+    assert An[0].nnz == Ad[0].nnz
+    for l in range(1, len(An)):
+        assert An[l].nnz > 2 * Ad[l].nnz
+    # coupling outside the coarse cliques on the first coarse level
+    d = pn.dofs[1]
+    allowed = set()
+    for c in range(len(pn.meshes[1].cell_faces)):
+        ids = d.free[d.cell_dofs(c)]
+        ids = ids[ids >= 0]
+        allowed.update((int(i), int(j)) for i in ids for j in ids)
+    coo = An[1].tocoo()
+    big = np.abs(coo.data) > 1e-12 * np.abs(coo.data).max()
+    outside = sum((int(i), int(j)) not in allowed for i, j in zip(coo.row[big], coo.col[big]))
+    assert outside > 0.5 * big.sum()

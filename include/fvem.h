@@ -66,7 +66,17 @@ typedef struct {
  *            (the hierarchy is nested, Sec. 5.2); NULL on the coarsest level.
  *  P         prolongation from level+1 to this level, n_dof x n_dof(level+1),
  *            diffusion-free: every row of a DOF of cell c may only reference
- *            DOFs of cell parent[c] (Sec. 4); unused on the coarsest level. */
+ *            DOFs of cell parent[c] (Sec. 4); unused on the coarsest level.
+ *  dof_lattice optional [n_dof x 3]: integer coordinates of each DOF's
+ *            support point on the level's structured lattice (cells of
+ *            side 2^level h; the half-lattice of spacing 2^(level-1) h for
+ *            k = 2, the vertex lattice for k = 1), or -1 where the point is
+ *            off the lattice.  With it, rows that equal their lattice
+ *            class's stencil are applied without stored columns or values
+ *            (the compact storage of regular-grid regions that Sec. 7
+ *            suggests); NULL keeps every row in sliced storage.
+ *  lattice_n lattice points per axis (2 N / 2^level + 1 for k = 2,
+ *            N / 2^level + 1 for k = 1). */
 typedef struct {
     int64_t n_dof;
     int64_t n_cells;
@@ -74,6 +84,8 @@ typedef struct {
     const int32_t *cell_dof;
     const int32_t *parent;
     fvem_csr P;
+    const int32_t *dof_lattice;
+    int32_t lattice_n;
 } fvem_level_desc;
 
 /* The problem: hierarchy plus the finest level's element operators.
@@ -104,16 +116,7 @@ typedef struct {
  *                 length of vc_val.
  *  cell_geom      [n_cells x 5] centroid x_E, h_E (diameter) and volume of
  *                 each level-0 cell (with vc_off).
- *  vert_xyz       [n_vert x 3] velocity vertex coordinates (with vc_off).
- *  dof_lattice    optional [n_dof of level 0 x 3]: integer coordinates of each
- *                 level-0 DOF's support point on the structured lattice of
- *                 the background grid (the half-lattice of spacing h/2 for
- *                 k = 2, the vertex lattice for k = 1), or -1 where the point
- *                 is off the lattice.  With it, rows that equal their lattice
- *                 class's stencil are applied without stored columns or
- *                 values (Sec. 7's compact storage for regular regions);
- *                 NULL keeps every row in sliced storage.
- *  lattice_n      lattice points per axis (2 N + 1 or N + 1). */
+ *  vert_xyz       [n_vert x 3] velocity vertex coordinates (with vc_off). */
 typedef struct {
     int32_t n_levels;
     const fvem_level_desc *levels;
@@ -133,8 +136,6 @@ typedef struct {
     int64_t vc_len;
     const double *cell_geom;
     const double *vert_xyz;
-    const int32_t *dof_lattice;
-    int32_t lattice_n;
 } fvem_grid_desc;
 
 /* Hierarchy options.  Zero-initialised fields take the defaults in brackets. */
@@ -147,9 +148,9 @@ typedef struct {
     int64_t small_level_rows;   /* levels with at most this many rows share each row among 16
                                    lanes instead of one lane per row [131072]; < 0: never */
     int32_t max_templates;      /* value templates per operator [4096]; < 0: none */
-    double lattice_min_fraction; /* with dof_lattice: use the lattice stencil layout on level 0
-                                    when at least this fraction of its rows are stencil rows
-                                    [0.5]; < 0: never */
+    double lattice_min_fraction; /* with dof_lattice: use the lattice stencil layout on a level
+                                    below the coarsest when at least this fraction of its rows
+                                    are stencil rows [0.5]; < 0: never */
     int32_t column_codes;       /* 0: 16-bit column codes for every slice whose columns allow
                                    them [default]; < 0: int32 columns everywhere */
     int32_t galerkin_general;   /* nonzero: form every coarse operator as P^T A P by sparse
@@ -192,7 +193,11 @@ typedef struct fvem_hierarchy fvem_hierarchy;
  * Assembles K from the element blocks, forms A_{l+1} = P_l^T A_l P_l
  * element-wise per coarse cell, transposes P, computes Chebyshev bounds,
  * FP32 copies and the coarsest-level factorisation, and preallocates every
- * solve buffer.  Errors: INVALID (bad sizes, indices out of range, a P row
+ * solve buffer.  Where a coarse level below the coarsest gives dof_lattice,
+ * the element blocks of translated copies of a lattice-aligned coarse cell
+ * that agree to 1e-12 of their largest entry (rounding of the product) are
+ * replaced by the first such block, so that translated rows are equal and
+ * can be applied as lattice stencils.  Errors: INVALID (bad sizes, indices out of range, a P row
  * that references a DOF outside its cell's parent, non-finite values), OOM,
  * HIP, NOT_SPD.  On success *out owns all device memory. */
 fvem_status fvem_hierarchy_build(const fvem_grid_desc *g, const fvem_options *o,

@@ -135,7 +135,8 @@ struct DevSELL {
 };
 
 struct Level {
-  int64_t n = 0;
+  int64_t n = 0;      // vector length: DOFs, or lattice slots with holes and then the rest
+  int64_t ndof = 0;   // the level's DOFs
   DevSELL A;
   DevSELL P, R;   // transfers in their own length-sorted row order (rowmap)
   std::vector<int32_t> order;   // level order: order[internal] = caller's DOF index
@@ -302,7 +303,7 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_template
   return d;
 }
 
-// Level 0 on the lattice layout: the stencil rows go to the class tables,
+// A level on the lattice layout: the stencil rows go to the class tables,
 // every other row (off the lattice, or not matching its class's stencil)
 // to sliced storage in its own length-sorted order with a row map into the
 // padded level order.  A is in the caller's order; inv maps caller DOF ->
@@ -501,6 +502,13 @@ static double *static_scratch_address(int device) {
   return addr[device];
 }
 
+// Translated coarse element blocks that agree to this fraction of their
+// largest entry are one block up to rounding: an entry of P_f^T K_f P_f sums
+// at most 27 x 27 products per child over 8 children (k = 2), so two
+// evaluation orders differ by at most about 5832 unit roundoffs (6.5e-13) of
+// the summed magnitudes.
+constexpr double CANONICAL_TOL = 1e-12;
+
 static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options *o, hipStream_t s) {
   check(g != nullptr, "null descriptor");
   check(g->n_levels >= 1 && g->levels, "n_levels < 1");
@@ -670,6 +678,18 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     if (hbad != big)
       throw SetupError{FVEM_ERR_INVALID, "prolongation row " + std::to_string(hbad) +
                                              " references a DOF outside the parent cell (not diffusion-free)"};
+    if (g->levels[l + 1].dof_lattice && l + 2 < L) {
+      // translated copies of a lattice-aligned coarse cell get one block, so
+      // that their rows assemble to equal values (stencil rows); done
+      // whether or not the level then takes the lattice layout, so that both
+      // layouts hold one operator
+      const int64_t nrep = canonical_blocks(C, g->levels[l + 1].dof_lattice, knext, CANONICAL_TOL);
+      if (nrep && ooff[ncc])
+        HIPCHECK(hipMemcpyAsync(d_out, knext.val.data(), sizeof(double) * ooff[ncc], hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      progress("hierarchy: level %d, %lld translated element blocks made identical", l + 1,
+               static_cast<long long>(nrep));
+    }
     A[l + 1] = assemble_blocks(nc, nc, C, C, knext);
     progress("hierarchy: Galerkin level %d, n=%lld nnz=%lld", l + 1, static_cast<long long>(nc),
              static_cast<long long>(A[l + 1].rp.back()));
@@ -684,27 +704,35 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   // operator, transfer and per-DOF array is renumbered into it
   constexpr int64_t ORDER_WINDOW = 4096;
   std::vector<std::vector<int32_t>> inv(L);
-  // level 0 on the lattice layout when the descriptor gives lattice
-  // coordinates and at least half of the rows are stencil rows
-  HostLattice lat0;
-  const bool lattice = L > 1 && g->dof_lattice && g->lattice_n > 0 && lattice_min >= 0 &&
-                       lattice_layout(A[0], g->dof_lattice, g->lattice_n, lattice_min, &lat0);
-  if (lattice)
-    progress("hierarchy: level 0 lattice layout, %lld of %lld rows on stencils, %lld tiles",
-             static_cast<long long>(lat0.n_stencil), static_cast<long long>(h->n0),
-             static_cast<long long>(lat0.tiles.size()));
+  // a level below the coarsest takes the lattice layout when the
+  // descriptor gives its lattice coordinates and enough of its rows are
+  // stencil rows; its order is then the padded lattice order (slots with
+  // holes, then the DOFs off the lattice) and A stays in the caller's order
+  std::vector<HostLattice> lat(L);
+  std::vector<char> on_lattice(L, 0);
+  for (int l = 0; l + 1 < L; ++l) {
+    const fvem_level_desc &ld = g->levels[l];
+    if (!ld.dof_lattice || ld.lattice_n <= 0 || lattice_min < 0) continue;
+    on_lattice[l] = lattice_layout(A[l], ld.dof_lattice, ld.lattice_n, lattice_min, &lat[l]);
+    if (on_lattice[l])
+      progress("hierarchy: level %d lattice layout, %lld of %lld rows on stencils, %lld tiles", l,
+               static_cast<long long>(lat[l].n_stencil), static_cast<long long>(A[l].n_rows),
+               static_cast<long long>(lat[l].tiles.size()));
+  }
   for (int l = 0; l < L; ++l) {
-    if (l == 0 && lattice) {
-      h->lv[0].order = lat0.order;           // slots with holes, then the DOFs off the lattice
-      inv[0] = inverse(lat0.order, h->n0);
-      continue;                              // A[0] stays in the caller's order
+    h->lv[l].ndof = A[l].n_rows;
+    if (on_lattice[l]) {
+      h->lv[l].order = lat[l].order;
+      inv[l] = inverse(lat[l].order, A[l].n_rows);
+      continue;
     }
     h->lv[l].order = window_order(A[l], ORDER_WINDOW);
     inv[l] = inverse(h->lv[l].order);
     A[l] = permute(A[l], h->lv[l].order, &inv[l]);
   }
   h->nl0 = static_cast<int64_t>(h->lv[0].order.size());
-  for (int l = 0; l + 1 < L; ++l) P[l] = permute(P[l], h->lv[l].order, &inv[l + 1]);
+  for (int l = 0; l + 1 < L; ++l)
+    P[l] = permute(P[l], h->lv[l].order, &inv[l + 1], static_cast<int64_t>(h->lv[l + 1].order.size()));
   if (g->n_vert > 0) Bh = permute(Bh, h->lv[0].order, nullptr);
   std::vector<int32_t> comp_caller = comp0;
   {
@@ -722,17 +750,18 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     Level &V = h->lv[l];
     std::vector<double> dinv;
     int64_t mark = h->mem.bytes;
-    if (l == 0 && lattice) {
-      V.n = h->nl0;
-      upload_lattice_level(h, V, A[0], lat0, inv[0], max_templates, codes, s);
+    if (on_lattice[l]) {
+      V.n = static_cast<int64_t>(V.order.size());
+      upload_lattice_level(h, V, A[l], lat[l], inv[l], max_templates, codes, s);
       dinv.assign(V.n, 0.0);
+      const HostCSR &Al = A[l];
 #pragma omp parallel for schedule(dynamic, 4096)
       for (int64_t r = 0; r < V.n; ++r) {
         const int32_t i = V.order[r];
         if (i < 0) continue;
         double d = 0.0;
-        for (int64_t k = A[0].rp[i]; k < A[0].rp[i + 1]; ++k)
-          if (A[0].ci[k] == i) d = A[0].v[k];
+        for (int64_t k = Al.rp[i]; k < Al.rp[i + 1]; ++k)
+          if (Al.ci[k] == i) d = Al.v[k];
         dinv[r] = d > 0.0 ? 1.0 / d : 0.0;
       }
     } else {
@@ -1370,7 +1399,7 @@ fvem_status fvem_vcycle_bytes(fvem_hierarchy *h, int32_t precision, int64_t *byt
   int64_t total = 0;
   for (int l = 0; l + 1 < h->nlev; ++l) {
     const Level &L = h->lv[l];
-    const int64_t n = l == 0 ? h->n0 : L.n, nn = h->lv[l + 1].n;
+    const int64_t n = L.ndof, nn = h->lv[l + 1].ndof;
     const int64_t deg = static_cast<int64_t>(L.ca.size());
     // 2 deg applications of A_l (deg - 1 pre-smoothing steps after the
     // first, the residual, deg post-smoothing steps); vectors: the first
@@ -1544,7 +1573,7 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
   }
   return guard([&] {
     const DevSELL &A = h->lv[level].A;
-    if (n_rows) *n_rows = level == 0 ? h->n0 : A.n;
+    if (n_rows) *n_rows = h->lv[level].ndof;
     if (nnz) *nnz = A.nnz + A.st.nnz;
     if (!row_ptr && !col && !val) return FVEM_OK;
     // read back the sliced operator and return it in the caller's order
@@ -1610,7 +1639,7 @@ fvem_status fvem_level_matrix(fvem_hierarchy *h, int32_t level, int64_t *n_rows,
         }
       Ls = std::move(P);
     }
-    const int64_t ncaller = level == 0 ? h->n0 : h->lv[level].n;
+    const int64_t ncaller = h->lv[level].ndof;
     const HostCSR C = permute(Ls, inverse(order, ncaller), &order, ncaller);
     if (row_ptr) std::copy(C.rp.begin(), C.rp.end(), row_ptr);
     if (col) std::copy(C.ci.begin(), C.ci.end(), col);
@@ -1649,8 +1678,7 @@ struct fvem_grid {
   fvem::grid::Output out;
   std::vector<fvem_level_desc> levels;
   std::vector<double> xflat;
-  std::vector<int32_t> lat;   // lattice coordinates of the level-0 DOFs (-1: off the lattice)
-  int32_t lat_n = 0;
+  std::vector<std::vector<int32_t>> lat;   // per level: lattice coordinates of its DOFs (-1: off the lattice)
 };
 
 extern "C" {
@@ -1715,25 +1743,32 @@ fvem_status fvem_grid_build_ex(const double *V, int64_t nv, const int32_t *F, in
         d.P.val = P.v.data();
       }
     }
-    {
-      // support points on the background lattice: the half-lattice of
-      // spacing h/2 for k = 2 (vertices, edge midpoints, face and cell
-      // centres of uncut cubes), the vertex lattice for k = 1
-      const auto &L0 = o.levels[0];
-      const double scale = k == 2 ? 2.0 * N : static_cast<double>(N);
-      g->lat_n = static_cast<int32_t>(scale) + 1;
-      g->lat.assign(3 * L0.n_dof, -1);
-      for (int64_t i = 0; i < L0.n_dof; ++i) {
+    // support points on each level's lattice: cells of side 2^l h, the
+    // half-lattice of spacing 2^(l-1) h for k = 2 (vertices, edge midpoints,
+    // face and cell centres of whole cubes), the vertex lattice for k = 1
+    g->lat.resize(L);
+    for (int l = 0; l < L; ++l) {
+      const auto &lv = o.levels[l];
+      const int64_t div = int64_t(1) << l;
+      const int64_t steps = (k == 2 ? 2 * int64_t(N) : int64_t(N)) / div;
+      if (steps < 2 || (k == 2 ? 2 * int64_t(N) : int64_t(N)) % div) continue;
+      const double scale = static_cast<double>(steps);
+      const int32_t lat_n = static_cast<int32_t>(steps) + 1;
+      std::vector<int32_t> &lat = g->lat[l];
+      lat.assign(3 * lv.n_dof, -1);
+      for (int64_t i = 0; i < lv.n_dof; ++i) {
         int32_t c[3];
         bool on = true;
         for (int d = 0; d < 3 && on; ++d) {
-          const double q = L0.dof_point[3 * i + d] * scale, r = std::nearbyint(q);
-          on = std::fabs(q - r) < 1e-7 && r >= 0 && r < g->lat_n;
+          const double q = lv.dof_point[3 * i + d] * scale, r = std::nearbyint(q);
+          on = std::fabs(q - r) < 1e-7 && r >= 0 && r < lat_n;
           c[d] = static_cast<int32_t>(r);
         }
         if (on)
-          for (int d = 0; d < 3; ++d) g->lat[3 * i + d] = c[d];
+          for (int d = 0; d < 3; ++d) lat[3 * i + d] = c[d];
       }
+      g->levels[l].dof_lattice = lat.data();
+      g->levels[l].lattice_n = lat_n;
     }
     g->xflat.resize(3 * o.X.size());
     for (size_t i = 0; i < o.X.size(); ++i) {
@@ -1770,8 +1805,6 @@ fvem_status fvem_grid_describe(fvem_grid *g, fvem_grid_desc *d) {
   d->vc_len = static_cast<int64_t>(o.vc_val.size());
   d->cell_geom = o.cell_geom.data();
   d->vert_xyz = g->xflat.data();
-  d->dof_lattice = g->lat.empty() ? nullptr : g->lat.data();
-  d->lattice_n = g->lat_n;
   return FVEM_OK;
 }
 

@@ -2,6 +2,8 @@
 #include "setup_host.hpp"
 
 #include <algorithm>
+#include <array>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -539,6 +541,78 @@ inline uint64_t morton3(uint32_t a, uint32_t b, uint32_t c) {
 }
 
 }  // namespace
+
+int64_t canonical_blocks(const HostCells &C, const int32_t *lat, HostBlocks &K, double tol) {
+  const int64_t nc = C.n_cells;
+  // local DOFs of each aligned cell in lexicographic order of their lattice
+  // offsets from the cell's lowest corner; the offsets form the group key
+  std::vector<std::vector<int32_t>> perm(nc);
+  std::vector<uint64_t> key(nc, 0);
+  std::vector<uint8_t> aligned(nc, 0);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t p0 = C.ptr[c], m = C.ptr[c + 1] - p0;
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+    bool ok = m > 0;
+    for (int64_t q = 0; q < m && ok; ++q) {
+      const int32_t d = C.dof[p0 + q];
+      ok = d >= 0 && lat[3 * d] >= 0;
+      for (int a = 0; a < 3 && ok; ++a) lo[a] = std::min(lo[a], lat[3 * d + a]);
+    }
+    if (!ok) continue;
+    std::vector<std::array<int32_t, 4>> rel(m);
+    for (int64_t q = 0; q < m; ++q) {
+      const int32_t d = C.dof[p0 + q];
+      rel[q] = {lat[3 * d] - lo[0], lat[3 * d + 1] - lo[1], lat[3 * d + 2] - lo[2], static_cast<int32_t>(q)};
+    }
+    std::sort(rel.begin(), rel.end());
+    uint64_t hsh = mix64(static_cast<uint64_t>(m));
+    for (int64_t q = 0; q < m; ++q) {
+      if (q > 0 && rel[q][0] == rel[q - 1][0] && rel[q][1] == rel[q - 1][1] && rel[q][2] == rel[q - 1][2]) ok = false;
+      hsh = mix64(hsh ^ mix64((static_cast<uint64_t>(rel[q][0]) << 42) ^ (static_cast<uint64_t>(rel[q][1]) << 21) ^
+                              static_cast<uint64_t>(rel[q][2])));
+    }
+    if (!ok) continue;
+    perm[c].resize(m);
+    for (int64_t q = 0; q < m; ++q) perm[c][q] = rel[q][3];
+    key[c] = hsh;
+    aligned[c] = 1;
+  }
+  // the first cell of each pattern (increasing cell id) is its representative
+  std::unordered_map<uint64_t, int64_t> first;
+  std::vector<int64_t> rep(nc, -1);
+  for (int64_t c = 0; c < nc; ++c)
+    if (aligned[c]) rep[c] = first.emplace(key[c], c).first->second;
+  int64_t replaced = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : replaced)
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t r = rep[c];
+    if (r < 0 || r == c) continue;
+    const int64_t m = C.ptr[c + 1] - C.ptr[c];
+    if (C.ptr[r + 1] - C.ptr[r] != m) continue;
+    // same offsets (a hash collision leaves the block alone)
+    bool same = true;
+    for (int64_t q = 0; q < m && same; ++q) {
+      const int32_t a = C.dof[C.ptr[c] + perm[c][q]], b = C.dof[C.ptr[r] + perm[r][q]];
+      for (int x = 0; x < 3; ++x)
+        same = same && lat[3 * a + x] - lat[3 * C.dof[C.ptr[c] + perm[c][0]] + x] ==
+                           lat[3 * b + x] - lat[3 * C.dof[C.ptr[r] + perm[r][0]] + x];
+    }
+    if (!same) continue;
+    const double *Br = &K.val[K.off[r]];
+    double *Bc = &K.val[K.off[c]];
+    double big = 0, diff = 0;
+    for (int64_t i = 0; i < m * m; ++i) big = std::max(big, std::fabs(Br[i]));
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t j = 0; j < m; ++j)
+        diff = std::max(diff, std::fabs(Bc[perm[c][i] * m + perm[c][j]] - Br[perm[r][i] * m + perm[r][j]]));
+    if (diff > tol * big) continue;
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t j = 0; j < m; ++j) Bc[perm[c][i] * m + perm[c][j]] = Br[perm[r][i] * m + perm[r][j]];
+    ++replaced;
+  }
+  return replaced;
+}
 
 bool lattice_layout(const HostCSR &A, const int32_t *lat, int32_t lat_n, double min_fraction, HostLattice *L) {
   *L = HostLattice();

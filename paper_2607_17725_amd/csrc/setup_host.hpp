@@ -164,6 +164,16 @@ struct HostLattice {
 // min_fraction of the rows are stencil rows.
 bool lattice_layout(const HostCSR &A, const int32_t *lat, int32_t lat_n, double min_fraction, HostLattice *L);
 
+// Element blocks of translated copies of one lattice-aligned cell differ only
+// by rounding (their prolongation rows were evaluated at different absolute
+// coordinates, their children summed in a different order).  Cells whose DOFs
+// all lie on the lattice lat [n_dof x 3] are grouped by the lattice pattern of
+// their DOFs; a block that agrees with its group's first block to tol times
+// that block's largest entry is replaced by it (in its own local order), so
+// that translated rows assemble to equal values.  Returns the number of blocks
+// replaced.
+int64_t canonical_blocks(const HostCells &C, const int32_t *lat, HostBlocks &K, double tol);
+
 // max_i sum_j |a_ij| / sqrt(a_ii a_jj): Gershgorin bound of D^-1/2 A D^-1/2,
 // which has the spectrum of D^-1 A and stays bounded by the row length for
 // symmetric positive semi-definite A even where some a_ii are tiny.

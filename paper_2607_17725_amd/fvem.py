@@ -39,7 +39,8 @@ class _CSR(ctypes.Structure):
 
 class _Level(ctypes.Structure):
     _fields_ = [("n_dof", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("cell_ptr", ctypes.c_void_p),
-                ("cell_dof", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("P", _CSR)]
+                ("cell_dof", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("P", _CSR),
+                ("dof_lattice", ctypes.c_void_p), ("lattice_n", ctypes.c_int32)]
 
 
 class _Grid(ctypes.Structure):
@@ -49,8 +50,7 @@ class _Grid(ctypes.Structure):
                 ("be_off", ctypes.c_void_p), ("be_val", ctypes.c_void_p), ("be_len", ctypes.c_int64),
                 ("component", ctypes.c_void_p), ("n_components", ctypes.c_int32),
                 ("vc_off", ctypes.c_void_p), ("vc_val", ctypes.c_void_p), ("vc_len", ctypes.c_int64),
-                ("cell_geom", ctypes.c_void_p), ("vert_xyz", ctypes.c_void_p),
-                ("dof_lattice", ctypes.c_void_p), ("lattice_n", ctypes.c_int32)]
+                ("cell_geom", ctypes.c_void_p), ("vert_xyz", ctypes.c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -175,9 +175,11 @@ class Hierarchy:
     """Solver hierarchy built from a problem description (host numpy arrays).
 
     ``desc`` keys: ``levels`` (list of dicts with n_dof, cell_ptr, cell_dof,
-    parent, P given as (row_ptr, col, val) or None), ``ke_ptr``, ``ke_val``,
-    ``n_vert``, ``cell_vptr``, ``cell_vert``, ``be_ptr``, ``be_val``,
-    ``component``, ``n_components``.
+    parent, P given as (row_ptr, col, val) or None, and optionally
+    dof_lattice [n_dof x 3] with lattice_n), ``ke_off``, ``ke_val``,
+    ``n_vert``, ``cell_vptr``, ``cell_vert``, ``be_off``, ``be_val``,
+    ``component``, ``n_components``, and the optional velocity blocks
+    ``vc_off``, ``vc_val``, ``cell_geom``, ``vert_xyz``.
     """
 
     def __init__(self, desc, stream=None, cheb_degree=5, cheb_lower=1.0 / 30.0, coarse_dense_max=16384,
@@ -209,6 +211,11 @@ class Hierarchy:
                 pa, pap = _arr(lv["parent"], np.int32)
                 keep.append(pa)
                 levels[l].parent = pap
+            if lv.get("dof_lattice") is not None:
+                la, lap = _arr(lv["dof_lattice"], np.int32)
+                keep.append(la)
+                levels[l].dof_lattice = lap
+                levels[l].lattice_n = int(lv["lattice_n"])
             if lv.get("P") is not None:
                 rp, ci, va = lv["P"]
                 rp, rpp = _arr(rp, np.int64)
@@ -222,7 +229,7 @@ class Hierarchy:
         for name, dt in (("ke_off", np.int64), ("ke_val", np.float64), ("cell_vptr", np.int64),
                          ("cell_vert", np.int32), ("be_off", np.int64), ("be_val", np.float64),
                          ("component", np.int32), ("vc_off", np.int64), ("vc_val", np.float64),
-                         ("cell_geom", np.float64), ("vert_xyz", np.float64), ("dof_lattice", np.int32)):
+                         ("cell_geom", np.float64), ("vert_xyz", np.float64)):
             if desc.get(name) is not None:
                 a, p = _arr(desc[name], dt)
                 keep.append(a)
@@ -232,7 +239,6 @@ class Hierarchy:
         g.vc_len = len(desc["vc_val"]) if desc.get("vc_val") is not None else 0
         g.n_vert = int(desc.get("n_vert", 0))
         g.n_components = int(desc.get("n_components", 0))
-        g.lattice_n = int(desc.get("lattice_n", 0))
         self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
                      small_level_rows, max_templates, lattice_min_fraction, galerkin_general, column_codes)
 
@@ -482,7 +488,9 @@ class Grid:
             lv = g.levels[l]
             cp = arr(lv.cell_ptr, lv.n_cells + 1, ctypes.c_int64)
             d = {"n_dof": lv.n_dof, "cell_ptr": cp, "cell_dof": arr(lv.cell_dof, int(cp[-1]), ctypes.c_int32),
-                 "parent": None, "P": None}
+                 "parent": None, "P": None,
+                 "dof_lattice": arr(lv.dof_lattice, 3 * lv.n_dof, ctypes.c_int32) if lv.dof_lattice else None,
+                 "lattice_n": lv.lattice_n}
             if l + 1 < g.n_levels:
                 d["parent"] = arr(lv.parent, lv.n_cells, ctypes.c_int32)
                 P = lv.P
@@ -500,10 +508,7 @@ class Grid:
                 "n_components": g.n_components,
                 "vc_off": arr(g.vc_off, nc0, ctypes.c_int64), "vc_val": arr(g.vc_val, g.vc_len, ctypes.c_double),
                 "cell_geom": arr(g.cell_geom, 5 * nc0, ctypes.c_double),
-                "vert_xyz": arr(g.vert_xyz, 3 * g.n_vert, ctypes.c_double),
-                "dof_lattice": (arr(g.dof_lattice, 3 * g.levels[0].n_dof, ctypes.c_int32)
-                                if g.dof_lattice else None),
-                "lattice_n": g.lattice_n}
+                "vert_xyz": arr(g.vert_xyz, 3 * g.n_vert, ctypes.c_double)}
 
     def __del__(self):
         g = getattr(self, "_g", None)

@@ -1,8 +1,9 @@
 // Checks of the library's host-side setup routines (sliced storage, level
 // order, permutation, transpose, block assembly, element-wise Galerkin
-// product, scaled Gershgorin bound) against dense brute force on small
-// random inputs.  Built with g++ by tests/test_host_setup.py; prints one line
-// per check and exits non-zero on the first failure.
+// product, scaled Gershgorin bound, canonical element blocks) against dense
+// brute force on small random inputs, or against hand-built cases.  Built
+// with g++ by tests/test_host_setup.py; prints one line per check and exits
+// non-zero on the first failure.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -381,6 +382,33 @@ int main() {
       A.rp[i + 1] = static_cast<int64_t>(A.ci.size());
     }
     expect(std::fabs(gershgorin_scaled(A) - 2.0) < 1e-14, "scaled Gershgorin bound");
+  }
+  {
+    // canonical blocks: four 2-DOF cells on a 1D lattice (x along the first
+    // coordinate), each cell's DOFs at x and x+1 but listed in either order;
+    // cell 1 is cell 0 translated with a 1e-15 perturbation, cell 2 differs
+    // by 1e-9, cell 3 has a different pattern (DOFs two apart), cell 4 has a
+    // DOF off the lattice
+    HostCells C;
+    C.n_cells = 5;
+    C.ptr = {0, 2, 4, 6, 8, 10};
+    C.dof = {0, 1, 3, 2, 4, 5, 6, 8, 9, 10};
+    std::vector<int32_t> lat = {0, 0, 0, 1, 0, 0, 2, 0, 0, 3, 0, 0, 4, 0, 0, 5, 0, 0,
+                                6, 0, 0, 7, 0, 0, 8, 0, 0, -1, -1, -1, 9, 0, 0};
+    HostBlocks K;
+    K.off = {0, 4, 8, 12, 16};
+    // cell 0 in order (x, x+1); cell 1 lists (x+1, x): its block is the
+    // transpose-permuted copy
+    K.val = {4.0, -1.0, -1.0, 2.0,
+             2.0, -1.0 + 1e-15, -1.0, 4.0,
+             4.0, -1.0 + 1e-9, -1.0, 2.0,
+             4.0, -1.0, -1.0, 2.0,
+             4.0, -1.0, -1.0, 2.0};
+    const int64_t n = canonical_blocks(C, lat.data(), K, 1e-12);
+    expect(n == 1, "canonical blocks: one translated copy replaced");
+    expect(K.val[4] == 2.0 && K.val[5] == -1.0 && K.val[6] == -1.0 && K.val[7] == 4.0,
+           "canonical blocks: the copy takes the first block in its own local order");
+    expect(K.val[9] == -1.0 + 1e-9, "canonical blocks: a block beyond the tolerance is kept");
   }
   std::printf("%d failure(s)\n", failures);
   return failures ? 1 : 0;

@@ -65,6 +65,7 @@ def describe(pb, canonical_cubes=True):
     for l in range(L):
         cp, cd = level_cells(pb, l)
         lv = {"n_dof": pb.dofs[l].n_free, "cell_ptr": cp, "cell_dof": cd, "parent": None, "P": None}
+        lv["dof_lattice"], lv["lattice_n"] = dof_lattice(pb, l)
         if l + 1 < L:
             lv["parent"] = np.asarray(pb.parents[l], dtype=np.int32)
             P = pb.P[l].tocsr()
@@ -90,7 +91,6 @@ def describe(pb, canonical_cubes=True):
         be_val.append(Bm.ravel())
         be_ptr.append(be_ptr[-1] + Bm.size)
     comp = np.full(pb.dofs[0].n_free, -1, dtype=np.int32)
-    lat, lat_n = dof_lattice(pb)
     for c, idx in enumerate(pb.null.floating):
         comp[idx] = c
     return {
@@ -103,7 +103,6 @@ def describe(pb, canonical_cubes=True):
         "vc_off": np.array(vc_ptr[:-1], dtype=np.int64), "vc_val": np.concatenate(vc_val),
         "cell_geom": np.array(geom, dtype=np.float64).ravel(),
         "vert_xyz": np.ascontiguousarray(pb.vertices, dtype=np.float64).ravel(),
-        "dof_lattice": lat, "lattice_n": lat_n,
     }
 
 
@@ -113,12 +112,16 @@ def dof_points(pb, level=0):
     return _all_points(pb, level)[pb.dofs[level].free_ids]
 
 
-def dof_lattice(pb):
-    """Integer lattice coordinates of the level-0 DOFs (-1 off the lattice):
-    the half-lattice of spacing h/2 for k = 2, the vertex lattice for k = 1."""
-    scale = 2 * pb.w.N if pb.k == 2 else pb.w.N
-    q = dof_points(pb) * scale
+def dof_lattice(pb, level=0):
+    """Integer lattice coordinates of a level's DOFs (-1 off the lattice) on
+    the lattice of cells of side 2^level h: the half-lattice of spacing
+    2^(level-1) h for k = 2, the vertex lattice for k = 1."""
+    span = 2 * pb.w.N if pb.k == 2 else pb.w.N
+    if span % 2 ** level or span // 2 ** level < 2:
+        return None, 0
+    steps = span // 2 ** level
+    q = dof_points(pb, level) * steps
     r = np.rint(q)
-    on = np.all(np.abs(q - r) < 1e-7, axis=1) & np.all((r >= 0) & (r <= scale), axis=1)
+    on = np.all(np.abs(q - r) < 1e-7, axis=1) & np.all((r >= 0) & (r <= steps), axis=1)
     lat = np.where(on[:, None], r, -1).astype(np.int32)
-    return lat.ravel(), int(scale + 1)
+    return lat.ravel(), int(steps + 1)

@@ -66,6 +66,17 @@ def test_stencil_layout_applies_K(name, N):
     rp, ci, va = on.level_matrix(0)
     Kr = sp.csr_matrix((va, ci, rp), shape=K.shape)
     assert abs(Kr - K).max() <= 1e-15 * abs(K).max()
+    # every coarser level: the layout chosen per level holds the same
+    # operator as sliced storage, value for value
+    for l in range(1, on.n_levels):
+        n = on.level_rows(l)
+        rp, ci, va = on.level_matrix(l)
+        A_on = sp.csr_matrix((va, ci, rp), shape=(n, n))
+        rp, ci, va = off.level_matrix(l)
+        A_off = sp.csr_matrix((va, ci, rp), shape=(n, n))
+        print(f"[gpu stencil] {name}@{N} level {l}: {on.level_stencil(l)}", flush=True)
+        assert off.level_stencil(l)["rows"] == 0
+        assert abs(A_on - A_off).max() == 0.0
 
 
 @pytest.mark.parametrize("name,N", CASES)

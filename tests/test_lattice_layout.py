@@ -80,10 +80,10 @@ def test_native_grid_layout(name, N, k, want, checker, tmp_path):
     V, F = w.mesh()
     g = fvem.Grid(V, F, w.N, w.k, levels=w.levels, dirichlet_top=w.dirichlet_top)
     desc = g.describe()
-    _run(checker, tmp_path, _assemble(desc), desc["dof_lattice"], desc["lattice_n"], want)
+    _run(checker, tmp_path, _assemble(desc), desc["levels"][0]["dof_lattice"], desc["levels"][0]["lattice_n"], want)
 
 
 def test_oracle_layout(c3_small, checker, tmp_path):
     from oracle_desc import describe
     desc = describe(c3_small)
-    _run(checker, tmp_path, _assemble(desc), desc["dof_lattice"], desc["lattice_n"], 0.05)
+    _run(checker, tmp_path, _assemble(desc), desc["levels"][0]["dof_lattice"], desc["levels"][0]["lattice_n"], 0.05)

@@ -157,6 +157,8 @@ def main():
                     help="value templates per operator (0: library default, <0: none)")
     ap.add_argument("--small-level-rows", type=int, default=0,
                     help="levels up to this many rows use the row-split SpMV (0: library default, <0: never)")
+    ap.add_argument("--lattice-min", type=float, default=0.0,
+                    help="smallest share of stencil rows for the lattice layout of a level (0: library default)")
     ap.add_argument("--prolongation", choices=["diffusion-free", "naive"], default="diffusion-free",
                     help="naive: the Sec. 4 ablation, with coarse operators from general sparse products")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -187,7 +189,8 @@ def main():
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     hier = fvem.Hierarchy(grid, stream=stream, small_level_rows=args.small_level_rows,
-                          max_templates=args.max_templates, galerkin_general=naive)
+                          max_templates=args.max_templates, galerkin_general=naive,
+                          lattice_min_fraction=args.lattice_min)
     torch.cuda.synchronize()
     t_hier = time.perf_counter() - t0
     n0 = hier.n_dof

@@ -393,6 +393,59 @@ fvem_status fvem_grid_level_points(fvem_grid *g, int32_t level, const double **d
 
 void fvem_grid_destroy(fvem_grid *g);
 
+/* ---------------------------------------------------------------- transport
+ * The steps on either side of the solve in the simulation loop (Algorithm 1):
+ * P2G (Sec. 3.2), the buoyancy force (Sec. 3.2), G2P (Sec. 3.3) and particle
+ * advection (Sec. 3.3), on the finest level of a native grid.  A transport
+ * copies the grid's BSP trees, boundary triangles and cell geometry to the
+ * current device; the grid may be destroyed afterwards.  Positions are
+ * [n x 3] FP64 device arrays on the unit cube; cell fields are the
+ * projected velocities of fvem_project_velocity (12 per level-0 cell: three
+ * components on [1, (x - x_E)/h_E]); vertex fields follow the grid's velocity
+ * vertices.  Calls enqueue on hip_stream; fvem_p2g and fvem_advect on one
+ * transport must not overlap (else BUSY).  Errors: INVALID, HIP, OOM. */
+typedef struct fvem_transport fvem_transport;
+
+fvem_status fvem_transport_create(const fvem_grid *g, void *hip_stream, fvem_transport **out);
+void fvem_transport_destroy(fvem_transport *t);
+
+/* Level-0 cell holding each point (the background cell's cube, or the leaf
+ * of its BSP tree, Sec. 5.1), -1 in a solid part or outside the unit cube.
+ * cell_dev: [n] int32. */
+fvem_status fvem_locate(fvem_transport *t, int64_t n, const double *x_dev, int32_t *cell_dev, void *hip_stream);
+
+/* P2G (Sec. 3.2): out[i, :] = sum_p f[p, :] w_ip / sum_p w_ip with
+ * w_ip = max(0, 1 - |x_p - x_i|^2 / h^2)^3 over the particles, for every
+ * velocity vertex i; 0 where no particle is within h.  f_dev: [n x m]
+ * row-major, 1 <= m <= 8; out_dev: [n_vert x m].  Sums run in a fixed order
+ * (bitwise reproducible).  Scratch of n entries is kept and grows with n. */
+fvem_status fvem_p2g(fvem_transport *t, int64_t n, const double *x_dev, const double *f_dev, int32_t m,
+                     double *out_dev, void *hip_stream);
+
+/* The force step of Sec. 3.2 at the vertices: from the P2G fields
+ * f [n_vert x m] (columns u_x, u_y, u_z, density, temperature, ...) writes
+ * u' [3 n_vert] = u + dt (-alpha density + beta temperature) e_z
+ * (Boussinesq buoyancy, +z up). */
+fvem_status fvem_buoyancy(fvem_transport *t, const double *f_dev, int32_t m, double alpha, double beta, double dt,
+                          double *u_dev, void *hip_stream);
+
+/* G2P (Sec. 3.3): for every particle with ghost[p] == 0 that lies in a fluid
+ * cell E, with du = s_new_E(x_p) - s_old_E(x_p),
+ * u_p <- a (u_p + du) + (1 - a) s_new_E(x_p) (the FLIP/PIC blend, a in
+ * [0, 1]).  s_old is the projection of the P2G velocity before the force. */
+fvem_status fvem_g2p(fvem_transport *t, int64_t n, const double *x_dev, const uint8_t *ghost_dev, double *u_dev,
+                     const double *s_new_dev, const double *s_old_dev, double a_flip, void *hip_stream);
+
+/* Advection (Sec. 3.3): moves every non-ghost particle that lies in the fluid
+ * by midpoint RK2 through the cell field s over dt, in
+ * max(1, ceil(dt v N)) substeps (CFL number 1; v the largest |s(x_p)|); a
+ * stage that ends outside the fluid is mirrored in the plane of the first
+ * boundary triangle or box wall it crosses (up to 4 times), else ends where
+ * it began.  *substeps returns the count; more than max_substeps is INVALID.
+ * Waits for the speed reduction (one host synchronisation). */
+fvem_status fvem_advect(fvem_transport *t, int64_t n, double *x_dev, const uint8_t *ghost_dev, const double *s_dev,
+                        double dt, int32_t max_substeps, int32_t *substeps, void *hip_stream);
+
 const char *fvem_last_error(void);
 
 #ifdef __cplusplus

@@ -23,6 +23,7 @@
 
 #include "../../include/fvem.h"
 #include "kernels.hpp"
+#include "transport.hpp"
 #include "grid.hpp"
 #include "setup_host.hpp"
 #include "progress.hpp"
@@ -1839,5 +1840,190 @@ fvem_status fvem_grid_level_points(fvem_grid *g, int32_t level, const double **d
 }
 
 void fvem_grid_destroy(fvem_grid *g) { delete g; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- transport
+//
+// Point location, P2G, G2P and advection on a native grid's finest level
+// (Algorithm 1, Sec. 3.2-3.3).  The structure copies the grid's BSP trees,
+// triangle lists and cell geometry to the device; P2G scratch grows with the
+// particle count.
+
+struct fvem_transport {
+  fvem::DevMem mem;
+  fvem::TransportView view;
+  int device = 0;
+  int32_t *cell_count = nullptr, *cell_start = nullptr, *chunk = nullptr;
+  int32_t *order = nullptr;
+  int64_t order_cap = 0;
+  std::unique_ptr<fvem::DevMem> order_mem;
+  unsigned long long *vmax = nullptr;
+  std::atomic<int> busy{0};
+};
+
+namespace fvem {
+
+struct TransportBusy {
+  fvem_transport *t;
+  bool ok;
+  explicit TransportBusy(fvem_transport *tt) : t(tt) {
+    int z = 0;
+    ok = t->busy.compare_exchange_strong(z, 1);
+  }
+  ~TransportBusy() {
+    if (ok) t->busy.store(0);
+  }
+};
+
+static void transport_device(const fvem_transport *t) {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  check(dev == t->device, "transport used on another device than the one it was created on");
+}
+
+}  // namespace fvem
+
+extern "C" {
+
+fvem_status fvem_transport_create(const fvem_grid *g, void *hip_stream, fvem_transport **out) {
+  if (!g || !out) {
+    g_last_error = "null argument";
+    return FVEM_ERR_INVALID;
+  }
+  *out = nullptr;
+  return guard([&] {
+    const auto &o = g->out;
+    check(!o.levels.empty() && !o.loc_bg.empty(), "grid has no finest-level locator");
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    auto t = std::make_unique<fvem_transport>();
+    HIPCHECK(hipGetDevice(&t->device));
+    int64_t N3 = static_cast<int64_t>(o.loc_bg.size());
+    int32_t N = static_cast<int32_t>(std::llround(std::cbrt(static_cast<double>(N3))));
+    check(static_cast<int64_t>(N) * N * N == N3, "locator is not N^3");
+    TransportView &v = t->view;
+    v.N = N;
+    v.bg = t->mem.upload(o.loc_bg, s);
+    v.tree_root = t->mem.upload(o.loc_tree_root, s);
+    v.plane = t->mem.upload(o.loc_plane, s);
+    v.child = t->mem.upload(o.loc_child, s);
+    v.leaf_cell = t->mem.upload(o.loc_cell, s);
+    v.tri_ptr = t->mem.upload(o.tri_ptr, s);
+    v.tri_id = t->mem.upload(o.tri_id, s);
+    v.tri_xyz = t->mem.upload(o.tri_xyz, s);
+    v.cell_geom = t->mem.upload(o.cell_geom, s);
+    v.vert_xyz = t->mem.upload(g->xflat, s);
+    v.n_vert = o.n_vert;
+    t->cell_count = t->mem.alloc<int32_t>(N3 + 1);
+    t->cell_start = t->mem.alloc<int32_t>(N3 + 1);
+    t->chunk = t->mem.alloc<int32_t>(p2g_chunks(N));
+    t->vmax = t->mem.alloc<unsigned long long>(1);
+    HIPCHECK(hipStreamSynchronize(s));
+    *out = t.release();
+    return FVEM_OK;
+  });
+}
+
+void fvem_transport_destroy(fvem_transport *t) { delete t; }
+
+fvem_status fvem_locate(fvem_transport *t, int64_t n, const double *x_dev, int32_t *cell_dev, void *hip_stream) {
+  if (!t || n < 0 || (n > 0 && (!x_dev || !cell_dev))) {
+    g_last_error = "bad transport or arguments";
+    return FVEM_ERR_INVALID;
+  }
+  return guard([&] {
+    transport_device(t);
+    locate(t->view, n, x_dev, cell_dev, static_cast<hipStream_t>(hip_stream));
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_p2g(fvem_transport *t, int64_t n, const double *x_dev, const double *f_dev, int32_t m,
+                     double *out_dev, void *hip_stream) {
+  if (!t || n < 0 || m < 1 || m > 8 || !out_dev || (n > 0 && (!x_dev || !f_dev))) {
+    g_last_error = "bad transport or arguments (1 to 8 fields per particle)";
+    return FVEM_ERR_INVALID;
+  }
+  if (n >= (int64_t(1) << 31)) {
+    g_last_error = "too many particles for int32 indices";
+    return FVEM_ERR_INVALID;
+  }
+  TransportBusy busy(t);
+  if (!busy.ok) {
+    g_last_error = "transport in use by another call";
+    return FVEM_ERR_BUSY;
+  }
+  return guard([&] {
+    transport_device(t);
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (n > t->order_cap) {
+      HIPCHECK(hipStreamSynchronize(s));
+      t->order_mem = std::make_unique<DevMem>();
+      t->order = t->order_mem->alloc<int32_t>(n);
+      t->order_cap = n;
+    }
+    p2g(t->view, n, x_dev, f_dev, m, out_dev, t->cell_count, t->cell_start, t->chunk, t->order, s);
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_buoyancy(fvem_transport *t, const double *f_dev, int32_t m, double alpha, double beta, double dt,
+                          double *u_dev, void *hip_stream) {
+  if (!t || m < 5 || !f_dev || !u_dev) {
+    g_last_error = "bad transport or arguments (fields: u, density, temperature)";
+    return FVEM_ERR_INVALID;
+  }
+  return guard([&] {
+    transport_device(t);
+    buoyancy(t->view.n_vert, f_dev, m, alpha, beta, dt, u_dev, static_cast<hipStream_t>(hip_stream));
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_g2p(fvem_transport *t, int64_t n, const double *x_dev, const uint8_t *ghost_dev, double *u_dev,
+                     const double *s_new_dev, const double *s_old_dev, double a_flip, void *hip_stream) {
+  if (!t || n < 0 || (n > 0 && (!x_dev || !ghost_dev || !u_dev || !s_new_dev || !s_old_dev)) ||
+      !(a_flip >= 0.0 && a_flip <= 1.0)) {
+    g_last_error = "bad transport or arguments (a_flip in [0, 1])";
+    return FVEM_ERR_INVALID;
+  }
+  return guard([&] {
+    transport_device(t);
+    g2p(t->view, n, x_dev, ghost_dev, u_dev, s_new_dev, s_old_dev, a_flip, static_cast<hipStream_t>(hip_stream));
+    return FVEM_OK;
+  });
+}
+
+fvem_status fvem_advect(fvem_transport *t, int64_t n, double *x_dev, const uint8_t *ghost_dev, const double *s_dev,
+                        double dt, int32_t max_substeps, int32_t *substeps, void *hip_stream) {
+  if (!t || n < 0 || (n > 0 && (!x_dev || !ghost_dev || !s_dev)) || !(dt >= 0.0) || max_substeps < 1) {
+    g_last_error = "bad transport or arguments";
+    return FVEM_ERR_INVALID;
+  }
+  TransportBusy busy(t);
+  if (!busy.ok) {
+    g_last_error = "transport in use by another call";
+    return FVEM_ERR_BUSY;
+  }
+  return guard([&] {
+    transport_device(t);
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    unsigned long long bits = 0;
+    HIPCHECK(hipMemcpyAsync(t->vmax, &bits, sizeof(bits), hipMemcpyHostToDevice, s));
+    grid_speed_max(t->view, n, x_dev, ghost_dev, s_dev, t->vmax, s);
+    HIPCHECK(hipMemcpyAsync(&bits, t->vmax, sizeof(bits), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    double vmax;
+    std::memcpy(&vmax, &bits, sizeof(vmax));
+    if (!std::isfinite(vmax)) throw SetupError{FVEM_ERR_NONFINITE, "non-finite grid velocity"};
+    // CFL number 1 on the background spacing h = 1 / N
+    const double want = std::ceil(dt * vmax * t->view.N);
+    if (want > max_substeps) throw SetupError{FVEM_ERR_INVALID, "advection needs more than max_substeps substeps"};
+    const int n_sub = std::max(1, static_cast<int>(want));
+    advect(t->view, n, x_dev, ghost_dev, s_dev, dt, n_sub, s);
+    if (substeps) *substeps = n_sub;
+    return FVEM_OK;
+  });
+}
 
 }  // extern "C"

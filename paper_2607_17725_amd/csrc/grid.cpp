@@ -133,6 +133,8 @@ struct BuilderImpl {
   double total_area = 0;
   std::vector<int32_t> tree_of;
   std::vector<Tree> trees;
+  std::vector<int64_t> tri_cells;                // background cells with boundary triangles
+  std::vector<std::vector<int32_t>> tri_lists;   // their triangles
   std::vector<uint8_t> bg_fluid;
   std::vector<Level> levels;
   std::vector<std::vector<int32_t>> parents;   // per level: fine cell -> coarse cell
@@ -276,9 +278,9 @@ struct BuilderImpl {
   }
 
   void build_forest() {
-    std::vector<std::vector<int32_t>> cell_tris;
-    std::vector<int64_t> cells;
-    associate(cell_tris, cells);
+    associate(tri_lists, tri_cells);
+    const std::vector<std::vector<int32_t>> &cell_tris = tri_lists;
+    const std::vector<int64_t> &cells = tri_cells;
     std::vector<Tree> all(cells.size());
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < static_cast<int64_t>(cells.size()); ++q) all[q] = build_tree(cells[q], cell_tris[q]);
@@ -1436,6 +1438,62 @@ struct BuilderImpl {
       o.dof_kind[fi] = static_cast<int8_t>(raw_kind(M, r));
     }
     o.n_trees = static_cast<int64_t>(trees.size());
+    export_locator(o);
+  }
+
+  // point location and triangle lists of the finest level (see Output)
+  void export_locator(Output &o) const {
+    const Level &l0 = levels[0];
+    const Mesh &M = l0.mesh;
+    const int64_t N3 = static_cast<int64_t>(N) * N * N;
+    o.loc_bg.assign(N3, -1);
+    o.loc_tree_root.resize(trees.size());
+    int64_t nn = 0;
+    for (size_t t = 0; t < trees.size(); ++t) {
+      o.loc_tree_root[t] = static_cast<int32_t>(nn);
+      nn += static_cast<int64_t>(trees[t].nodes.size());
+    }
+    if (nn >= (int64_t(1) << 31)) throw std::runtime_error("too many BSP nodes for int32 indices");
+    o.loc_plane.assign(4 * nn, 0.0);
+    o.loc_child.assign(2 * nn, -1);
+    o.loc_cell.assign(nn, -1);
+    for (size_t t = 0; t < trees.size(); ++t) {
+      const int32_t r = o.loc_tree_root[t];
+      o.loc_bg[trees[t].bg] = -2 - static_cast<int32_t>(t);
+      for (size_t a = 0; a < trees[t].nodes.size(); ++a) {
+        const Node &nd = trees[t].nodes[a];
+        if (nd.child[0] < 0) continue;
+        const int64_t gq = r + static_cast<int64_t>(a);
+        o.loc_plane[4 * gq] = nd.n.x;
+        o.loc_plane[4 * gq + 1] = nd.n.y;
+        o.loc_plane[4 * gq + 2] = nd.n.z;
+        o.loc_plane[4 * gq + 3] = nd.d;
+        o.loc_child[2 * gq] = r + nd.child[0];
+        o.loc_child[2 * gq + 1] = r + nd.child[1];
+      }
+    }
+    for (int64_t c = 0; c < M.nc(); ++c) {
+      const Tile &T = l0.tiles[M.ctile[c]];
+      if (T.type == 1) {
+        if (T.hi[0] - T.lo[0] != 1) throw std::runtime_error("finest-level cube larger than one background cell");
+        o.loc_bg[bgi(N, T.lo[0], T.lo[1], T.lo[2])] = static_cast<int32_t>(c);
+      } else {
+        o.loc_cell[o.loc_tree_root[T.tree] + T.node] = static_cast<int32_t>(c);
+      }
+    }
+    o.tri_ptr.assign(N3 + 1, 0);
+    for (size_t q = 0; q < tri_cells.size(); ++q) o.tri_ptr[tri_cells[q] + 1] = static_cast<int64_t>(tri_lists[q].size());
+    for (int64_t b = 0; b < N3; ++b) o.tri_ptr[b + 1] += o.tri_ptr[b];
+    o.tri_id.resize(o.tri_ptr[N3]);
+    for (size_t q = 0; q < tri_cells.size(); ++q)
+      std::copy(tri_lists[q].begin(), tri_lists[q].end(), o.tri_id.begin() + o.tri_ptr[tri_cells[q]]);
+    o.tri_xyz.resize(9 * TF.size());
+    for (size_t t = 0; t < TF.size(); ++t)
+      for (int c = 0; c < 3; ++c) {
+        o.tri_xyz[9 * t + 3 * c] = TV[TF[t][c]].x;
+        o.tri_xyz[9 * t + 3 * c + 1] = TV[TF[t][c]].y;
+        o.tri_xyz[9 * t + 3 * c + 2] = TV[TF[t][c]].z;
+      }
   }
 };
 

@@ -54,6 +54,20 @@ struct Output {
   std::vector<int8_t> dof_kind;   // 0 vertex, 1 edge, 2 face, 3 cell
   int64_t n_shared_blocks = 0;
   int64_t n_trees = 0;
+  // point location on the finest level: per background cell (index
+  // (i N + j) N + k) the level-0 cube cell it is, -1 (no fluid cell), or
+  // -2 - t for BSP tree t; tree t's nodes start at tree_root[t]; an inner
+  // node splits by plane n.x = d (node_plane: n, d) into child[0] (n.x < d)
+  // and child[1]; a leaf holds its level-0 cell or -1 (solid)
+  std::vector<int32_t> loc_bg;
+  std::vector<int32_t> loc_tree_root;
+  std::vector<double> loc_plane;    // 4 per node
+  std::vector<int32_t> loc_child;   // 2 per node, -1 at leaves
+  std::vector<int32_t> loc_cell;    // per node: the leaf's cell or -1
+  // boundary triangles overlapping each background cell (CSR over N^3)
+  std::vector<int64_t> tri_ptr;
+  std::vector<int32_t> tri_id;
+  std::vector<double> tri_xyz;     // 9 per boundary triangle: its corners
 };
 
 void build_grid(const Input &in, Output *out);

@@ -82,7 +82,8 @@ EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_app
            "fvem_project_velocity", "fvem_project_velocity_adjoint", "fvem_velocity_loss", "fvem_hierarchy_cells",
            "fvem_level_storage", "fvem_level_bytes", "fvem_project_noalloc", "fvem_level_stencil",
            "fvem_transfer_storage", "fvem_vcycle_bytes", "fvem_level_slices",
-           "fvem_memory_breakdown", "fvem_grid_build_ex"]
+           "fvem_memory_breakdown", "fvem_grid_build_ex", "fvem_transport_create", "fvem_transport_destroy",
+           "fvem_locate", "fvem_p2g", "fvem_buoyancy", "fvem_g2p", "fvem_advect"]
 
 _lib = None
 
@@ -153,6 +154,20 @@ def load(path=LIB_PATH):
     lib.fvem_grid_level_points.restype = ctypes.c_int
     lib.fvem_grid_destroy.argtypes = [vp]
     lib.fvem_grid_destroy.restype = None
+    lib.fvem_transport_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    lib.fvem_transport_create.restype = ctypes.c_int
+    lib.fvem_transport_destroy.argtypes = [vp]
+    lib.fvem_transport_destroy.restype = None
+    lib.fvem_locate.argtypes = [vp, i64, vp, vp, vp]
+    lib.fvem_locate.restype = ctypes.c_int
+    lib.fvem_p2g.argtypes = [vp, i64, vp, vp, i32, vp, vp]
+    lib.fvem_p2g.restype = ctypes.c_int
+    lib.fvem_buoyancy.argtypes = [vp, vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp]
+    lib.fvem_buoyancy.restype = ctypes.c_int
+    lib.fvem_g2p.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.c_double, vp]
+    lib.fvem_g2p.restype = ctypes.c_int
+    lib.fvem_advect.argtypes = [vp, i64, vp, vp, vp, ctypes.c_double, i32, ctypes.POINTER(i32), vp]
+    lib.fvem_advect.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -621,3 +636,101 @@ def chain_loss_and_grad(hier, u0, eps, targets, store_dtype=None, tol=1e-10, pre
             hier.apply(OP_AVT, gu_next, out=gs, accumulate=True)
         gu_next, _ = hier.project_velocity_adjoint(gs, tol=tol, precision=precision)
     return total, gu_next, {"checkpoint_bytes": peak, "steps": K}
+
+
+class Transport:
+    """P2G, buoyancy, G2P and advection on a native grid's finest level
+    (the steps around the solve in Algorithm 1).  Arrays are float64 (ghost
+    flags uint8, cells int32) contiguous tensors on the current device."""
+
+    def __init__(self, grid, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise FvemError(2, "no GPU visible")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n_vert = grid.n_vert
+        t = ctypes.c_void_p()
+        _check(load().fvem_transport_create(grid._g, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(t)))
+        self._t = t
+
+    def __del__(self):
+        t = getattr(self, "_t", None)
+        if t is not None and _lib is not None:
+            _lib.fvem_transport_destroy(t)
+            self._t = None
+
+    def _arr(self, a, shape, dtype, what):
+        import torch
+        if not isinstance(a, torch.Tensor) or a.dtype != dtype or a.device != self.device or \
+                not a.is_contiguous() or tuple(a.shape) != tuple(shape):
+            raise ValueError(f"{what}: expected a contiguous {dtype} tensor of shape {tuple(shape)} on {self.device}")
+        return ctypes.c_void_p(a.data_ptr())
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def locate(self, x):
+        import torch
+        n = x.shape[0]
+        cell = torch.empty(n, dtype=torch.int32, device=self.device)
+        _check(load().fvem_locate(self._t, n, self._arr(x, (n, 3), torch.float64, "x"),
+                                  self._arr(cell, (n,), torch.int32, "cell"), self._s()))
+        return cell
+
+    def p2g(self, x, f):
+        import torch
+        n, m = f.shape
+        out = torch.empty((self.n_vert, m), dtype=torch.float64, device=self.device)
+        _check(load().fvem_p2g(self._t, n, self._arr(x, (n, 3), torch.float64, "x"),
+                               self._arr(f, (n, m), torch.float64, "f"), m,
+                               self._arr(out, (self.n_vert, m), torch.float64, "out"), self._s()))
+        return out
+
+    def buoyancy(self, f, alpha, beta, dt):
+        import torch
+        m = f.shape[1]
+        u = torch.empty(3 * self.n_vert, dtype=torch.float64, device=self.device)
+        _check(load().fvem_buoyancy(self._t, self._arr(f, (self.n_vert, m), torch.float64, "f"), m, float(alpha),
+                                    float(beta), float(dt), self._arr(u, (3 * self.n_vert,), torch.float64, "u"),
+                                    self._s()))
+        return u
+
+    def g2p(self, x, ghost, u, s_new, s_old, a_flip):
+        import torch
+        n = x.shape[0]
+        nc = s_new.shape[0]
+        _check(load().fvem_g2p(self._t, n, self._arr(x, (n, 3), torch.float64, "x"),
+                               self._arr(ghost, (n,), torch.uint8, "ghost"), self._arr(u, (n, 3), torch.float64, "u"),
+                               self._arr(s_new, (nc,), torch.float64, "s_new"),
+                               self._arr(s_old, (nc,), torch.float64, "s_old"), float(a_flip), self._s()))
+        return u
+
+    def advect(self, x, ghost, s, dt, max_substeps=64):
+        import torch
+        n = x.shape[0]
+        sub = ctypes.c_int32()
+        _check(load().fvem_advect(self._t, n, self._arr(x, (n, 3), torch.float64, "x"),
+                                  self._arr(ghost, (n,), torch.uint8, "ghost"),
+                                  self._arr(s, (s.shape[0],), torch.float64, "s"), float(dt), int(max_substeps),
+                                  ctypes.byref(sub), self._s()))
+        return x, sub.value
+
+
+def smoke_step(hier, transport, x, u, rho, temp, ghost, dt, a_flip=0.95, alpha=0.0, beta=1.0, tol=1e-8,
+               precision=PREC_MIXED):
+    """One simulation step of Algorithm 1 on the GPU: P2G, buoyancy, the
+    projection, G2P and advection.  x and u ([n, 3]) are updated in place;
+    rho, temp ([n]) ride with the particles.  Each step is one library call;
+    this function only sequences them."""
+    import torch
+    f = torch.cat([u, rho[:, None], temp[:, None]], dim=1).contiguous()
+    fv = transport.p2g(x, f)
+    u_grid = fv[:, :3].contiguous().view(-1)
+    u_forced = transport.buoyancy(fv, alpha, beta, dt)
+    s_new, st = hier.project_velocity(u_forced, tol=tol, precision=precision)
+    s_old = hier.apply(OP_PI1, u_grid)
+    transport.g2p(x, ghost, u, s_new, s_old, a_flip)
+    _, n_sub = transport.advect(x, ghost, s_new, dt)
+    return {"vertex": fv, "u_forced": u_forced, "s_new": s_new, "s_old": s_old, "substeps": n_sub,
+            "iterations": st["iterations"]}

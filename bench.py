@@ -140,6 +140,46 @@ print(json.dumps({{"n_dof": int(n), "s_per_solve": dt, "iterations": its[0], "so
     }
 
 
+def time_smoke_step(grid, hier, w, stream):
+    """One simulation step of Algorithm 1 with eight particles per background
+    cell, each phase timed on its own (synchronised), after one untimed step."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2607_17725_amd import fvem
+    x, u, rho, temp = synth.seeded_particles(w.N, seed=0)
+    tr = fvem.Transport(grid, stream=stream)
+    X = torch.as_tensor(x, device="cuda")
+    ghost = (tr.locate(X) < 0).to(torch.uint8)
+    g = ghost.cpu().numpy().astype(bool)
+    u[g], rho[g], temp[g] = 0.0, 0.0, 0.0
+    U, R, Tm = (torch.as_tensor(np.ascontiguousarray(a), device="cuda") for a in (u, rho, temp))
+    dt, a_flip, alpha, beta = 0.01, 0.95, 0.5, 2.0
+    fvem.smoke_step(hier, tr, X.clone(), U.clone(), R, Tm, ghost, dt, a_flip, alpha, beta)
+    torch.cuda.synchronize()
+    ms = {}
+
+    def timed(name, fn):
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ms[name] = (time.perf_counter() - t0) * 1e3
+        return r
+
+    f = torch.cat([U, R[:, None], Tm[:, None]], dim=1).contiguous()
+    fv = timed("p2g", lambda: tr.p2g(X, f))
+    u_grid = fv[:, :3].contiguous().view(-1)
+    u_forced = timed("buoyancy", lambda: tr.buoyancy(fv, alpha, beta, dt))
+    s_new, st = timed("projection", lambda: hier.project_velocity(u_forced, tol=w.tol))
+    s_old = timed("pi1", lambda: hier.apply(fvem.OP_PI1, u_grid))
+    timed("g2p", lambda: tr.g2p(X, ghost, U, s_new, s_old, a_flip))
+    _, n_sub = timed("advect", lambda: tr.advect(X, ghost, s_new, dt))
+    out = {"particles": int(len(x)), "ghosts": int(g.sum()), "dt": dt, "substeps": n_sub,
+           "projection_iterations": st["iterations"], "ms": ms, "ms_total": sum(ms.values())}
+    log(f"smoke step: {len(x)} particles, " + ", ".join(f"{k} {v:.2f} ms" for k, v in ms.items()))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +201,9 @@ def main():
                     help="smallest share of stencil rows for the lattice layout of a level (0: library default)")
     ap.add_argument("--prolongation", choices=["diffusion-free", "naive"], default="diffusion-free",
                     help="naive: the Sec. 4 ablation, with coarse operators from general sparse products")
+    ap.add_argument("--smoke-step", action="store_true",
+                    help="also time one simulation step (P2G, buoyancy, projection, G2P, advection) of 8 particles "
+                         "per background cell")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB buffer 3 times (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -302,6 +345,9 @@ def main():
                             "max_rel_residual": max(s["rel_residual"] for s in sta),
                             "input": "N(0,1) pressure sensitivities, seeds 500+"}
         log(f"adjoint: {len(G) / dad:.3f} solves/s")
+
+    if args.smoke_step:
+        extra["smoke_step"] = time_smoke_step(grid, hier, w, stream)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -7,7 +7,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfvem.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["api.hip", "kernels.hip", "sell.hip", "transport.hip", "setup_host.cpp", "geom.cpp", "vem.cpp", "grid.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "sell.hip", "transport.hip", "elem.hip", "setup_host.cpp", "geom.cpp", "vem.cpp", "grid.cpp"]
 
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 arithmetic
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

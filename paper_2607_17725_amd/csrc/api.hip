@@ -24,6 +24,7 @@
 #include "../../include/fvem.h"
 #include "kernels.hpp"
 #include "transport.hpp"
+#include "elem.hpp"
 #include "grid.hpp"
 #include "setup_host.hpp"
 #include "progress.hpp"
@@ -69,16 +70,6 @@ struct DevMem {
   ~DevMem() {
     for (void *p : ptrs) (void)hipFree(p);
   }
-};
-
-struct DevCSR {
-  int64_t n = 0, m = 0, nnz = 0;
-  int64_t *rp = nullptr;
-  int32_t *ci = nullptr;
-  double *v64 = nullptr;
-  float *v32 = nullptr;
-  DevCSRView<double> d() const { return {n, m, nnz, rp, ci, v64}; }
-  DevCSRView<float> f() const { return {n, m, nnz, rp, ci, v32}; }
 };
 
 // Level operator in the sliced layout; one column array serves both value
@@ -156,13 +147,13 @@ struct fvem_hierarchy {
   int device = 0;
   int nlev = 0;
   std::vector<fvem::Level> lv;
-  fvem::DevCSR B, BT;
   int64_t nvert = 0, n0 = 0;   // n0: the caller's level-0 DOFs
   int64_t nl0 = 0;             // level-0 vector length (lattice slots with holes, then the rest)
   int32_t *perm0 = nullptr, *iperm0 = nullptr;   // level-0 order and its inverse (device)
-  // velocity operators on cell fields (12 values per level-0 cell)
+  // divergence and velocity operators from the level-0 element blocks (cell
+  // fields: 12 values per level-0 cell)
+  fvem::ElemView el;
   int64_t ncell_v = 0;
-  fvem::DevCSR Pi, PiT, Gr, GrT, Ms, Av, AvT;
   double *vs1 = nullptr, *vs2 = nullptr;
   int32_t *comp0 = nullptr;
   int32_t *compc = nullptr;   // component of each DOF in the caller's order
@@ -229,21 +220,6 @@ static HostCSR csr_of(const fvem_csr &M, int64_t rows, int64_t cols, const char 
   return A;
 }
 
-static DevCSR upload_csr(fvem_hierarchy *h, const HostCSR &A, bool f32, hipStream_t s) {
-  DevCSR d;
-  d.n = A.n_rows;
-  d.m = A.n_cols;
-  d.nnz = A.nnz();
-  d.rp = h->mem.upload(A.rp, s);
-  d.ci = h->mem.upload(A.ci, s);
-  d.v64 = h->mem.upload(A.v, s);
-  if (f32) {
-    d.v32 = h->mem.alloc<float>(d.nnz);
-    cast_f64_f32(d.nnz, d.v64, d.v32, s);
-  }
-  HIPCHECK(hipStreamSynchronize(s));   // the host arrays may be temporaries
-  return d;
-}
 
 static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_templates, bool codes, hipStream_t s) {
   HostSELL S = to_sell(A, max_templates > 0, 64, std::max(max_templates, 1), codes);
@@ -368,96 +344,84 @@ static std::vector<int32_t> inverse(const std::vector<int32_t> &order, int64_t n
   return inv;
 }
 
-// Velocity operators on cell fields (row 12 E + 4 c + a: component c,
-// coefficient a of cell E on the monomials [1, (x - x_E)/h_E]), assembled
-// as CSR from the per-cell blocks: Pi_1, grad Pi_k (columns in the level
-// order), the block-diagonal mass and the volume-weighted vertex average.
-static void build_velocity(fvem_hierarchy *h, const fvem_grid_desc *g, const HostCells &c0,
-                           const std::vector<int32_t> &inv0, hipStream_t s) {
-  const int64_t nc = c0.n_cells, nv = g->n_vert;
-  check(nv > 0 && g->vc_val && g->vc_len >= 0 && g->cell_geom && g->vert_xyz, "velocity data incomplete");
-  check(finite_all(g->vc_val, g->vc_len), "velocity blocks: non-finite value");
-  check(finite_all(g->cell_geom, 5 * nc), "cell geometry: non-finite value");
-  check(finite_all(g->vert_xyz, 3 * nv), "vertex coordinates: non-finite value");
-  std::vector<double> W(nv, 0.0);   // volume around each vertex
-  for (int64_t c = 0; c < nc; ++c) {
-    const int64_t nvE = g->cell_vptr[c + 1] - g->cell_vptr[c], nE = c0.ptr[c + 1] - c0.ptr[c];
-    check(g->vc_off[c] >= 0 && g->vc_off[c] + 4 * nvE + 12 * nE + 16 <= g->vc_len, "velocity block out of range");
-    check(g->cell_geom[5 * c + 3] > 0 && g->cell_geom[5 * c + 4] > 0, "cell diameter or volume not positive");
-    for (int64_t q = g->cell_vptr[c]; q < g->cell_vptr[c + 1]; ++q) W[g->cell_vert[q]] += g->cell_geom[5 * c + 4];
+// Level-0 operators applied from their element blocks (divergence B and, with
+// vc_off, the velocity operators): index lists per cell in the level order,
+// the descriptor's block arrays as given (cells of one shape share a block),
+// and the positions of every pressure slot and vertex among the cells'
+// lists, in increasing order, for the summation of shared outputs.
+static void build_elem(fvem_hierarchy *h, const fvem_grid_desc *g, const HostCells &c0,
+                       const std::vector<int32_t> &inv0, hipStream_t s) {
+  const int64_t nc = c0.n_cells, nv = g->n_vert, nl = h->nl0;
+  ElemView &E = h->el;
+  E.ncell = nc;
+  E.nl = nl;
+  E.nv = nv;
+  std::vector<int64_t> vptr(g->cell_vptr, g->cell_vptr + nc + 1);
+  std::vector<int32_t> vert(g->cell_vert, g->cell_vert + vptr[nc]);
+  std::vector<int32_t> cdof(c0.dof.size());
+  for (size_t e = 0; e < c0.dof.size(); ++e) cdof[e] = c0.dof[e] >= 0 ? inv0[c0.dof[e]] : -1;
+  // positions of each pressure slot among cdof and of each vertex among vert
+  std::vector<int64_t> pptr(nl + 1, 0), qptr(nv + 1, 0);
+  for (int32_t d : cdof)
+    if (d >= 0) pptr[d + 1]++;
+  for (int32_t v : vert) qptr[v + 1]++;
+  for (int64_t i = 0; i < nl; ++i) pptr[i + 1] += pptr[i];
+  for (int64_t i = 0; i < nv; ++i) qptr[i + 1] += qptr[i];
+  check(pptr[nl] < (int64_t(1) << 31) && static_cast<int64_t>(cdof.size()) < (int64_t(1) << 31) &&
+            3 * static_cast<int64_t>(vert.size()) < (int64_t(1) << 31),
+        "cell index lists too long for int32 positions");
+  std::vector<int32_t> ppos(pptr[nl]), qpos(qptr[nv]);
+  {
+    std::vector<int64_t> fp(pptr.begin(), pptr.end() - 1), fq(qptr.begin(), qptr.end() - 1);
+    for (size_t e = 0; e < cdof.size(); ++e)
+      if (cdof[e] >= 0) ppos[fp[cdof[e]]++] = static_cast<int32_t>(e);
+    for (size_t e = 0; e < vert.size(); ++e) qpos[fq[vert[e]]++] = static_cast<int32_t>(e);
   }
-  // rows 12 E + 4 c + a of cell E: lengths per cell, offsets, then a
-  // parallel fill (each cell writes only its own rows)
-  HostCSR Pi, Gr, Ms, AvT;
-  for (HostCSR *A : {&Pi, &Gr, &Ms, &AvT}) {
-    A->n_rows = 12 * nc;
-    A->rp.assign(12 * nc + 1, 0);
-  }
-  Pi.n_cols = 3 * nv;
-  Gr.n_cols = h->nl0;
-  Ms.n_cols = 12 * nc;
-  AvT.n_cols = 3 * nv;
-  for (int64_t c = 0; c < nc; ++c) {
-    const int64_t nvE = g->cell_vptr[c + 1] - g->cell_vptr[c];
-    int64_t nfree = 0;
-    for (int64_t q = c0.ptr[c]; q < c0.ptr[c + 1]; ++q) nfree += c0.dof[q] >= 0;
-    for (int r = 0; r < 12; ++r) {
-      const int64_t i = 12 * c + r;
-      Pi.rp[i + 1] = Pi.rp[i] + nvE;
-      Gr.rp[i + 1] = Gr.rp[i] + nfree;
-      Ms.rp[i + 1] = Ms.rp[i] + 4;
-      AvT.rp[i + 1] = AvT.rp[i] + nvE;
+  int64_t mark = h->mem.bytes;
+  E.cptr = h->mem.upload(c0.ptr, s);
+  E.cdof = h->mem.upload(cdof, s);
+  E.vptr = h->mem.upload(vptr, s);
+  E.vert = h->mem.upload(vert, s);
+  E.pptr = h->mem.upload(pptr, s);
+  E.ppos = h->mem.upload(ppos, s);
+  E.qptr = h->mem.upload(qptr, s);
+  E.qpos = h->mem.upload(qpos, s);
+  E.tmp = h->mem.alloc<double>(std::max<int64_t>(static_cast<int64_t>(cdof.size()), 3 * vptr[nc]));
+  std::vector<int64_t> be_off(g->be_off, g->be_off + nc);
+  std::vector<double> be_val(g->be_val, g->be_val + g->be_len);
+  E.be_off = h->mem.upload(be_off, s);
+  E.be_val = h->mem.upload(be_val, s);
+  h->mem_by_kind[3] += h->mem.bytes - mark;
+  if (g->vc_off) {
+    mark = h->mem.bytes;
+    check(g->vc_val && g->vc_len >= 0 && g->cell_geom && g->vert_xyz, "velocity data incomplete");
+    check(finite_all(g->vc_val, g->vc_len), "velocity blocks: non-finite value");
+    check(finite_all(g->cell_geom, 5 * nc), "cell geometry: non-finite value");
+    check(finite_all(g->vert_xyz, 3 * nv), "vertex coordinates: non-finite value");
+    std::vector<double> W(nv, 0.0);   // volume around each vertex
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t nvE = vptr[c + 1] - vptr[c], nE = c0.ptr[c + 1] - c0.ptr[c];
+      check(g->vc_off[c] >= 0 && g->vc_off[c] + 4 * nvE + 12 * nE + 16 <= g->vc_len, "velocity block out of range");
+      check(g->cell_geom[5 * c + 3] > 0 && g->cell_geom[5 * c + 4] > 0, "cell diameter or volume not positive");
+      for (int64_t q = vptr[c]; q < vptr[c + 1]; ++q) W[vert[q]] += g->cell_geom[5 * c + 4];
     }
+    std::vector<double> winv(nv, 0.0);
+    for (int64_t v = 0; v < nv; ++v) winv[v] = W[v] > 0 ? 1.0 / W[v] : 0.0;
+    std::vector<int64_t> vc_off(g->vc_off, g->vc_off + nc);
+    std::vector<double> vc_val(g->vc_val, g->vc_val + g->vc_len), geom(g->cell_geom, g->cell_geom + 5 * nc),
+        xyz(g->vert_xyz, g->vert_xyz + 3 * nv);
+    E.vc_off = h->mem.upload(vc_off, s);
+    E.vc_val = h->mem.upload(vc_val, s);
+    E.geom = h->mem.upload(geom, s);
+    E.xyz = h->mem.upload(xyz, s);
+    E.winv = h->mem.upload(winv, s);
+    h->ncell_v = nc;
+    h->vs1 = h->mem.alloc<double>(12 * nc);
+    h->vs2 = h->mem.alloc<double>(12 * nc);
+    h->mem_by_kind[4] += h->mem.bytes - mark;
   }
-  for (HostCSR *A : {&Pi, &Gr, &Ms, &AvT}) {
-    A->ci.resize(A->rp.back());
-    A->v.resize(A->rp.back());
-  }
-#pragma omp parallel for schedule(dynamic, 256)
-  for (int64_t c = 0; c < nc; ++c) {
-    const int64_t v0 = g->cell_vptr[c], nvE = g->cell_vptr[c + 1] - v0, nE = c0.ptr[c + 1] - c0.ptr[c];
-    const double *blk = g->vc_val + g->vc_off[c];
-    const double *pi1 = blk, *gk = blk + 4 * nvE, *m1 = blk + 4 * nvE + 12 * nE;
-    const double *geo = g->cell_geom + 5 * c;
-    std::vector<std::pair<int32_t, int32_t>> fr;   // (level-order column, local slot)
-    for (int64_t q = 0; q < nE; ++q) {
-      const int32_t d = c0.dof[c0.ptr[c] + q];
-      if (d >= 0) fr.emplace_back(inv0[d], static_cast<int32_t>(q));
-    }
-    std::sort(fr.begin(), fr.end());
-    for (int comp = 0; comp < 3; ++comp)
-      for (int a = 0; a < 4; ++a) {
-        const int64_t r = 12 * c + 4 * comp + a;
-        for (int64_t v = 0; v < nvE; ++v) {
-          const int32_t gv = g->cell_vert[v0 + v];
-          Pi.ci[Pi.rp[r] + v] = 3 * gv + comp;
-          Pi.v[Pi.rp[r] + v] = pi1[a * nvE + v];
-          const double za = a == 0 ? 1.0 : (g->vert_xyz[3 * gv + a - 1] - geo[a - 1]) / geo[3];
-          AvT.ci[AvT.rp[r] + v] = 3 * gv + comp;
-          AvT.v[AvT.rp[r] + v] = geo[4] / W[gv] * za;
-        }
-        for (size_t q = 0; q < fr.size(); ++q) {
-          Gr.ci[Gr.rp[r] + q] = fr[q].first;
-          Gr.v[Gr.rp[r] + q] = gk[(comp * 4 + a) * nE + fr[q].second];
-        }
-        for (int b2 = 0; b2 < 4; ++b2) {
-          Ms.ci[Ms.rp[r] + b2] = static_cast<int32_t>(12 * c + 4 * comp + b2);
-          Ms.v[Ms.rp[r] + b2] = m1[a * 4 + b2];
-        }
-      }
-  }
-  check(12 * nc < (int64_t(1) << 31) && 3 * nv < (int64_t(1) << 31), "cell field too large for int32 columns");
-  h->ncell_v = nc;
-  h->Pi = upload_csr(h, Pi, false, s);
-  h->PiT = upload_csr(h, transpose(Pi), false, s);
-  h->Gr = upload_csr(h, Gr, false, s);
-  h->GrT = upload_csr(h, transpose(Gr), false, s);
-  h->Ms = upload_csr(h, Ms, false, s);
-  h->AvT = upload_csr(h, AvT, false, s);
-  h->Av = upload_csr(h, transpose(AvT), false, s);
-  h->vs1 = h->mem.alloc<double>(12 * nc);
-  h->vs2 = h->mem.alloc<double>(12 * nc);
-  progress("hierarchy: velocity operators stored");
+  HIPCHECK(hipStreamSynchronize(s));   // the host arrays are temporaries
+  progress("hierarchy: element operators stored");
 }
 
 static void cheb_coefficients(Level &L, int deg, double lower) {
@@ -552,31 +516,18 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   // divergence
   h->nvert = g->n_vert;
   check(g->n_vert >= 0, "n_vert");
-  HostCSR Bh;
   if (g->n_vert > 0) {
     check(g->cell_vptr && g->cell_vert && g->be_off && g->be_val && g->be_len >= 0, "divergence blocks missing");
-    HostCells vc;
-    vc.n_cells = c0.n_cells;
-    vc.ptr.resize(c0.n_cells + 1);
-    vc.ptr[0] = 0;
-    std::vector<int32_t> vdof;
+    check(g->cell_vptr[0] == 0, "cell_vptr[0] must be 0");
     for (int64_t c = 0; c < c0.n_cells; ++c) {
-      for (int64_t k = g->cell_vptr[c]; k < g->cell_vptr[c + 1]; ++k) {
-        const int32_t v = g->cell_vert[k];
-        check(v >= 0 && v < g->n_vert, "cell vertex out of range");
-        for (int d = 0; d < 3; ++d) vdof.push_back(3 * v + d);
-      }
-      vc.ptr[c + 1] = static_cast<int64_t>(vdof.size());
-    }
-    vc.dof = std::move(vdof);
-    HostBlocks be;
-    be.off.assign(g->be_off, g->be_off + c0.n_cells);
-    for (int64_t c = 0; c < c0.n_cells; ++c)
-      check(be.off[c] >= 0 && be.off[c] + (c0.ptr[c + 1] - c0.ptr[c]) * (vc.ptr[c + 1] - vc.ptr[c]) <= g->be_len,
+      check(g->cell_vptr[c + 1] >= g->cell_vptr[c], "cell_vptr not increasing");
+      for (int64_t k = g->cell_vptr[c]; k < g->cell_vptr[c + 1]; ++k)
+        check(g->cell_vert[k] >= 0 && g->cell_vert[k] < g->n_vert, "cell vertex out of range");
+      const int64_t w = 3 * (g->cell_vptr[c + 1] - g->cell_vptr[c]);
+      check(g->be_off[c] >= 0 && g->be_off[c] + (c0.ptr[c + 1] - c0.ptr[c]) * w <= g->be_len,
             "divergence block out of range");
-    be.val.assign(g->be_val, g->be_val + g->be_len);
-    check(finite_all(be.val.data(), g->be_len), "divergence: non-finite value");
-    Bh = assemble_blocks(h->n0, 3 * g->n_vert, c0, vc, be);
+    }
+    check(finite_all(g->be_val, g->be_len), "divergence: non-finite value");
   }
   // components of level 0
   std::vector<int32_t> comp0(h->n0, -1);
@@ -734,7 +685,6 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   h->nl0 = static_cast<int64_t>(h->lv[0].order.size());
   for (int l = 0; l + 1 < L; ++l)
     P[l] = permute(P[l], h->lv[l].order, &inv[l + 1], static_cast<int64_t>(h->lv[l + 1].order.size()));
-  if (g->n_vert > 0) Bh = permute(Bh, h->lv[0].order, nullptr);
   std::vector<int32_t> comp_caller = comp0;
   {
     std::vector<int32_t> c(h->nl0, -1);
@@ -820,21 +770,10 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     h->mem_by_kind[2] += h->mem.bytes - mark;
     if (l + 1 < L) A[l] = HostCSR();   // the coarsest stays for the dense factorisation
   }
-  if (g->n_vert > 0) {
-    const int64_t mark = h->mem.bytes;
-    h->B = upload_csr(h, Bh, false, s);
-    h->BT = upload_csr(h, transpose(Bh), false, s);
-    h->mem_by_kind[3] += h->mem.bytes - mark;
-    progress("hierarchy: divergence stored");
-  }
   h->comp0 = h->mem.upload(comp0, s);
   h->compc = h->mem.upload(comp_caller, s);
   h->scratch = static_scratch_address(h->device);
-  if (g->vc_off) {
-    const int64_t mark = h->mem.bytes;
-    build_velocity(h, g, c0, inv[0], s);
-    h->mem_by_kind[4] += h->mem.bytes - mark;
-  }
+  if (g->n_vert > 0) build_elem(h, g, c0, inv[0], s);
   progress("hierarchy: operators uploaded");
 
   // coarsest level: dense semi-definite factorisation and generalised inverse
@@ -1143,26 +1082,26 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
   const int64_t n = h->n0, nl = h->nl0;
   fvem_status stt;
   if (kind == SOLVE_VELOCITY) {
-    spmv<double>(h->B.d(), in, h->q, s);
+    elem_apply(h->el, ELEM_B, in, h->q, false, 1.0, s);
     stt = pcg(h, h->q, h->lam, so, st, s);
     if (p_out) gather(n, h->iperm0, h->lam, p_out, s);
-    spmv<double>(h->Pi.d(), in, out, s);
-    residual<double>(h->Gr.d(), h->lam, out, out, s);   // s = Pi_1 u - G p
+    elem_apply(h->el, ELEM_PI, in, out, false, 1.0, s);
+    elem_apply(h->el, ELEM_G, h->lam, out, true, -1.0, s);   // s = Pi_1 u - G p
   } else if (kind == SOLVE_VELOCITY_ADJOINT) {
-    spmv_scaled(h->GrT.d(), in, h->q, -1.0, s);         // g_p = -G^T g_s (level order)
+    elem_apply(h->el, ELEM_GT, in, h->q, false, -1.0, s);   // g_p = -G^T g_s (level order)
     stt = pcg(h, h->q, h->lam, so, st, s);
-    spmv<double>(h->BT.d(), h->lam, out, s);
-    spmv_add<double>(h->PiT.d(), in, out, s);
+    elem_apply(h->el, ELEM_BT, h->lam, out, false, 1.0, s);
+    elem_apply(h->el, ELEM_PIT, in, out, true, 1.0, s);
   } else if (!adjoint) {
     const double *rhs = h->q;
-    if (velocity) spmv<double>(h->B.d(), in, h->q, s);
+    if (velocity) elem_apply(h->el, ELEM_B, in, h->q, false, 1.0, s);
     else gather(nl, h->perm0, in, h->q, s);
     stt = pcg(h, rhs, h->lam, so, st, s);
     gather(n, h->iperm0, h->lam, out, s);
   } else {
     gather(nl, h->perm0, in, h->q, s);
     stt = pcg(h, h->q, h->lam, so, st, s);
-    if (velocity) spmv<double>(h->BT.d(), h->lam, out, s);
+    if (velocity) elem_apply(h->el, ELEM_BT, h->lam, out, false, 1.0, s);
     else gather(n, h->iperm0, h->lam, out, s);
   }
   HIPCHECK(hipEventRecord(e1, s));
@@ -1331,7 +1270,7 @@ fvem_status fvem_velocity_loss(fvem_hierarchy *h, const double *s_dev, const dou
     check(h->ncell_v > 0, "no velocity operators in this hierarchy");
     const int64_t m = 12 * h->ncell_v;
     lincomb(m, 1.0, s_dev, -1.0, t_dev, h->vs1, s);     // d = s - t
-    spmv<double>(h->Ms.d(), h->vs1, h->vs2, s);          // w = M d
+    elem_apply(h->el, ELEM_M, h->vs1, h->vs2, false, 1.0, s);   // w = M d
     double d[1];
     dots_host_n(h, m, 1, h->vs1, h->vs2, nullptr, nullptr, nullptr, nullptr, d, s);
     if (!std::isfinite(d[0])) throw SetupError{FVEM_ERR_NONFINITE, "non-finite loss"};
@@ -1482,24 +1421,21 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
       check(op == FVEM_OP_BT || op == FVEM_OP_PI1 || op == FVEM_OP_PI1T || op == FVEM_OP_G || op == FVEM_OP_MASS ||
                 op == FVEM_OP_AV || op == FVEM_OP_AVT,
             "accumulation is not available for this operator");
-    auto csr = [&](const DevCSR &A, const double *xx) {
-      if (acc) spmv_add<double>(A.d(), xx, y, s);
-      else spmv<double>(A.d(), xx, y, s);
-    };
+    auto el = [&](ElemOp eo, const double *xx) { elem_apply(h->el, eo, xx, y, acc, 1.0, s); };
     switch (op) {
-      case FVEM_OP_PI1: csr(h->Pi, x); break;
-      case FVEM_OP_PI1T: csr(h->PiT, x); break;
+      case FVEM_OP_PI1: el(ELEM_PI, x); break;
+      case FVEM_OP_PI1T: el(ELEM_PIT, x); break;
       case FVEM_OP_G:
         gather(nl, h->perm0, x, h->p, s);
-        csr(h->Gr, h->p);
+        el(ELEM_G, h->p);
         break;
       case FVEM_OP_GT:
-        spmv<double>(h->GrT.d(), x, h->q, s);
+        elem_apply(h->el, ELEM_GT, x, h->q, false, 1.0, s);
         gather(n, h->iperm0, h->q, y, s);
         break;
-      case FVEM_OP_MASS: csr(h->Ms, x); break;
-      case FVEM_OP_AV: csr(h->Av, x); break;
-      case FVEM_OP_AVT: csr(h->AvT, x); break;
+      case FVEM_OP_MASS: el(ELEM_M, x); break;
+      case FVEM_OP_AV: el(ELEM_AV, x); break;
+      case FVEM_OP_AVT: el(ELEM_AVT, x); break;
       case FVEM_OP_K:
         gather(nl, h->perm0, x, h->p, s);
         spmv<double>(h->lv[0].A.d(), h->p, h->q, s);
@@ -1507,13 +1443,13 @@ fvem_status fvem_apply(fvem_hierarchy *h, int32_t op, const double *x, double *y
         break;
       case FVEM_OP_B:
         check(h->nvert > 0, "no divergence operator");
-        spmv<double>(h->B.d(), x, h->q, s);
+        elem_apply(h->el, ELEM_B, x, h->q, false, 1.0, s);
         gather(n, h->iperm0, h->q, y, s);
         break;
       case FVEM_OP_BT:
         check(h->nvert > 0, "no divergence operator");
         gather(nl, h->perm0, x, h->p, s);
-        csr(h->BT, h->p);
+        el(ELEM_BT, h->p);
         break;
       case FVEM_OP_VCYCLE:
       case FVEM_OP_VCYCLE32: {

@@ -33,9 +33,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sell_cheb_plates128_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_cheb_plates128_traffic.json")
+# the stencil kernel, its epilogue and view, and the host code that lays the
+# lattice tiles out
 LAYOUT_SOURCES = [os.path.join(ROOT, "paper_2607_17725_amd", "csrc", f)
-                  for f in ("sell.hip", "epilogues.hpp", "setup_host.cpp", "api.hip")]
+                  for f in ("sell.hip", "epilogues.hpp", "kernels.hpp", "setup_host.cpp")]
 
 
 def layout_hash():

@@ -391,6 +391,15 @@ fvem_status fvem_grid_info(fvem_grid *g, const double **vertices, int64_t *n_ver
 fvem_status fvem_grid_level_points(fvem_grid *g, int32_t level, const double **dof_points, const int8_t **dof_kind,
                                    int64_t *n_dof);
 
+/* Faces of finest-level cell `cell` as outward vertex cycles (velocity
+ * vertex ids, counter-clockwise seen from outside), the cell's convex
+ * boundary after the conforming overlay (Sec. 5.1).  With face_len and
+ * face_vert NULL only the counts are returned; otherwise face_len [cap_faces]
+ * receives each face's corner count and face_vert [cap_corners] the corners,
+ * face after face (INVALID when a capacity is too small). */
+fvem_status fvem_grid_cell_faces(fvem_grid *g, int64_t cell, int32_t *n_faces, int32_t *n_corners,
+                                 int32_t *face_len, int32_t *face_vert, int32_t cap_faces, int32_t cap_corners);
+
 void fvem_grid_destroy(fvem_grid *g);
 
 /* ---------------------------------------------------------------- transport

@@ -1775,6 +1775,27 @@ fvem_status fvem_grid_level_points(fvem_grid *g, int32_t level, const double **d
   return FVEM_OK;
 }
 
+fvem_status fvem_grid_cell_faces(fvem_grid *g, int64_t cell, int32_t *n_faces, int32_t *n_corners,
+                                 int32_t *face_len, int32_t *face_vert, int32_t cap_faces, int32_t cap_corners) {
+  if (!g || cell < 0 || cell + 1 >= static_cast<int64_t>(g->out.cell_face_ptr.size())) {
+    g_last_error = "bad grid or cell";
+    return FVEM_ERR_INVALID;
+  }
+  const auto &o = g->out;
+  const int64_t f0 = o.cell_face_ptr[cell], f1 = o.cell_face_ptr[cell + 1];
+  const int64_t nf = f1 - f0, nc = o.face_ptr[f1] - o.face_ptr[f0];
+  if (n_faces) *n_faces = static_cast<int32_t>(nf);
+  if (n_corners) *n_corners = static_cast<int32_t>(nc);
+  if (!face_len && !face_vert) return FVEM_OK;
+  if (!face_len || !face_vert || cap_faces < nf || cap_corners < nc) {
+    g_last_error = "face buffers missing or too small";
+    return FVEM_ERR_INVALID;
+  }
+  for (int64_t f = f0; f < f1; ++f) face_len[f - f0] = static_cast<int32_t>(o.face_ptr[f + 1] - o.face_ptr[f]);
+  std::copy(o.face_vert.begin() + o.face_ptr[f0], o.face_vert.begin() + o.face_ptr[f1], face_vert);
+  return FVEM_OK;
+}
+
 void fvem_grid_destroy(fvem_grid *g) { delete g; }
 
 }  // extern "C"

@@ -1439,6 +1439,20 @@ struct BuilderImpl {
     }
     o.n_trees = static_cast<int64_t>(trees.size());
     export_locator(o);
+    // outward face cycles of the finest cells
+    o.cell_face_ptr.assign(1, 0);
+    o.face_ptr.assign(1, 0);
+    o.face_vert.clear();
+    for (int64_t c = 0; c < M.nc(); ++c) {
+      for (int64_t q = M.cfptr[c]; q < M.cfptr[c + 1]; ++q) {
+        const int32_t f = M.cface[q];
+        const size_t at = o.face_vert.size();
+        o.face_vert.insert(o.face_vert.end(), M.fvert.begin() + M.fptr[f], M.fvert.begin() + M.fptr[f + 1]);
+        if (M.corient[q] < 0) std::reverse(o.face_vert.begin() + at, o.face_vert.end());
+        o.face_ptr.push_back(static_cast<int64_t>(o.face_vert.size()));
+      }
+      o.cell_face_ptr.push_back(static_cast<int64_t>(o.face_ptr.size()) - 1);
+    }
   }
 
   // point location and triangle lists of the finest level (see Output)

@@ -68,6 +68,11 @@ struct Output {
   std::vector<int64_t> tri_ptr;
   std::vector<int32_t> tri_id;
   std::vector<double> tri_xyz;     // 9 per boundary triangle: its corners
+  // faces of each finest-level cell as outward vertex cycles (velocity
+  // vertex ids): cell c's faces are cell_face_ptr[c] .. cell_face_ptr[c+1]),
+  // face f's corners face_vert[face_ptr[f] .. face_ptr[f+1])
+  std::vector<int64_t> cell_face_ptr, face_ptr;
+  std::vector<int32_t> face_vert;
 };
 
 void build_grid(const Input &in, Output *out);

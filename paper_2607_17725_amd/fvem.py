@@ -83,7 +83,7 @@ EXPORTS = ["fvem_hierarchy_build", "fvem_solve", "fvem_solve_adjoint", "fvem_app
            "fvem_level_storage", "fvem_level_bytes", "fvem_project_noalloc", "fvem_level_stencil",
            "fvem_transfer_storage", "fvem_vcycle_bytes", "fvem_level_slices",
            "fvem_memory_breakdown", "fvem_grid_build_ex", "fvem_transport_create", "fvem_transport_destroy",
-           "fvem_locate", "fvem_p2g", "fvem_buoyancy", "fvem_g2p", "fvem_advect"]
+           "fvem_locate", "fvem_p2g", "fvem_buoyancy", "fvem_g2p", "fvem_advect", "fvem_grid_cell_faces"]
 
 _lib = None
 
@@ -154,6 +154,8 @@ def load(path=LIB_PATH):
     lib.fvem_grid_level_points.restype = ctypes.c_int
     lib.fvem_grid_destroy.argtypes = [vp]
     lib.fvem_grid_destroy.restype = None
+    lib.fvem_grid_cell_faces.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp, i32, i32]
+    lib.fvem_grid_cell_faces.restype = ctypes.c_int
     lib.fvem_transport_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
     lib.fvem_transport_create.restype = ctypes.c_int
     lib.fvem_transport_destroy.argtypes = [vp]
@@ -475,6 +477,17 @@ class Grid:
                                                 shape=(self.n_dof, 3)).copy()
         self.dof_kind = np.ctypeslib.as_array(ctypes.cast(dk, ctypes.POINTER(ctypes.c_int8)),
                                               shape=(self.n_dof,)).copy()
+
+    def cell_faces(self, cell):
+        """Outward vertex cycles (arrays of vertex ids) of finest-level cell ``cell``."""
+        lib = load()
+        nf, nc = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.fvem_grid_cell_faces(self._g, int(cell), ctypes.byref(nf), ctypes.byref(nc), None, None, 0, 0))
+        lens = np.zeros(nf.value, dtype=np.int32)
+        verts = np.zeros(nc.value, dtype=np.int32)
+        _check(lib.fvem_grid_cell_faces(self._g, int(cell), None, None, lens.ctypes.data, verts.ctypes.data,
+                                        nf.value, nc.value))
+        return np.split(verts, np.cumsum(lens)[:-1])
 
     def level_points(self, level):
         """(points [n x 3], kinds [n]) of level ``level``'s free DOFs."""

@@ -158,6 +158,10 @@ typedef struct {
                                    beyond one coarse cell (the naive prolongation of Sec. 4);
                                    0: the element-wise product, which requires the
                                    diffusion-free structure [0] */
+    int32_t vcycle_graphs;      /* 0: replay each V-cycle as a HIP graph, captured at its first
+                                   use on a stream the hierarchy owns and joined to the caller's
+                                   stream by events [default]; < 0: launch its kernels one by
+                                   one on the caller's stream (profiled solves always do) */
 } fvem_options;
 
 typedef enum { FVEM_PREC_FP64 = 0, FVEM_PREC_MIXED = 1 } fvem_precision;
@@ -169,7 +173,9 @@ typedef struct {
     int32_t precision;      /* fvem_precision: FP32 V-cycle inside FP64 CG, or all FP64 */
     int32_t input;          /* fvem_input */
     int32_t replace_every;  /* true-residual replacement period [10] */
-    int32_t profile;        /* nonzero: time every finest-level Chebyshev launch (HIP events) */
+    int32_t profile;        /* 1: time every V-cycle and every finest-level Chebyshev launch
+                               (HIP events; V-cycles then launch kernel by kernel); 2: time
+                               only the V-cycles (graph replays stay on); 0: no timing */
 } fvem_solve_opts;
 
 typedef struct {

@@ -177,7 +177,19 @@ struct fvem_hierarchy {
   size_t evv_used = 0;
   std::vector<hipEvent_t> evs;   // pairs around the stencil launches of finest Chebyshev steps
   size_t evs_used = 0;
-  bool profiling = false;
+  bool profiling = false;         // HIP events around the finest-level launches (V-cycles run eagerly)
+  bool profile_vcycle = false;    // HIP events around every V-cycle
+  // V-cycles as HIP graphs: one per precision and buffer state (smoothing
+  // swaps each level's x buffers an odd number of times, so consecutive
+  // V-cycles alternate between two pointer states)
+  struct VGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<void *> before, after;   // level buffer pointers at capture and after it
+  };
+  bool use_graphs = true;
+  hipStream_t gstream = nullptr;         // capture and replay stream (default priority)
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  VGraph vg[4];                          // [precision][state]
 };
 
 namespace fvem {
@@ -487,6 +499,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const int max_templates = (o && o->max_templates != 0) ? o->max_templates : 4096;
   const double lattice_min = (o && o->lattice_min_fraction != 0) ? o->lattice_min_fraction : 0.5;
   const bool general = o && o->galerkin_general != 0;
+  h->use_graphs = !(o && o->vcycle_graphs < 0);
   const bool codes = !(o && o->column_codes < 0);
   HIPCHECK(hipGetDevice(&h->device));
   h->nlev = L;
@@ -945,6 +958,84 @@ static void vcycle(fvem_hierarchy *h, int l, hipStream_t s) {
   smooth<T>(h, l, false, s);
 }
 
+// pointers of every level's smoothing buffers of precision T (the state a
+// V-cycle's graph was captured in; each precision has its own buffers)
+template <typename T>
+static std::vector<void *> vcycle_state(fvem_hierarchy *h) {
+  std::vector<void *> v;
+  for (Level &L : h->lv) {
+    v.push_back(Vec<T>::x(L));
+    v.push_back(Vec<T>::xb(L));
+  }
+  return v;
+}
+
+template <typename T>
+static void set_vcycle_state(fvem_hierarchy *h, const std::vector<void *> &v) {
+  size_t k = 0;
+  for (Level &L : h->lv) {
+    Vec<T>::x(L) = static_cast<T *>(v[k++]);
+    Vec<T>::xb(L) = static_cast<T *>(v[k++]);
+  }
+}
+
+// One V-cycle on stream s.  Unprofiled V-cycles run as HIP graphs: the
+// first in each buffer state is captured on the hierarchy's own stream and
+// replayed from then on; events join that stream to s both ways.  No node
+// is a memset (fills are kernels).  A failed capture switches graphs off for
+// the handle and runs the V-cycle eagerly.
+template <typename T>
+static void run_vcycle(fvem_hierarchy *h, hipStream_t s) {
+  if (!h->use_graphs || h->profiling) {
+    vcycle<T>(h, 0, s);
+    return;
+  }
+  const std::vector<void *> cur = vcycle_state<T>(h);
+  const int base = sizeof(T) == 8 ? 2 : 0;
+  fvem_hierarchy::VGraph *g = nullptr;
+  for (int k = 0; k < 2 && !g; ++k)
+    if (h->vg[base + k].exec && h->vg[base + k].before == cur) g = &h->vg[base + k];
+  if (!h->gstream) {
+    HIPCHECK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&h->gev_in, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&h->gev_out, hipEventDisableTiming));
+  }
+  if (!g) {
+    fvem_hierarchy::VGraph *slot = !h->vg[base].exec ? &h->vg[base] : !h->vg[base + 1].exec ? &h->vg[base + 1] : nullptr;
+    if (!slot) throw SetupError{FVEM_ERR_HIP, "V-cycle graph: unexpected buffer state"};
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      try {
+        vcycle<T>(h, 0, h->gstream);
+      } catch (...) {
+        ok = false;
+      }
+      ok = hipStreamEndCapture(h->gstream, &graph) == hipSuccess && ok && graph;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok) {
+      h->use_graphs = false;
+      set_vcycle_state<T>(h, cur);
+      vcycle<T>(h, 0, s);
+      return;
+    }
+    slot->exec = exec;
+    slot->before = cur;
+    slot->after = vcycle_state<T>(h);
+    g = slot;
+  }
+  HIPCHECK(hipEventRecord(h->gev_in, s));
+  HIPCHECK(hipStreamWaitEvent(h->gstream, h->gev_in, 0));
+  HIPCHECK(hipGraphLaunch(g->exec, h->gstream));
+  HIPCHECK(hipEventRecord(h->gev_out, h->gstream));
+  HIPCHECK(hipStreamWaitEvent(s, h->gev_out, 0));
+  set_vcycle_state<T>(h, g->after);
+}
+
 // z = M r (level-0 input r, FP64), projected
 static void precondition(fvem_hierarchy *h, const double *r, double *z, bool mixed, double rnorm, hipStream_t s) {
   Level &L0 = h->lv[0];
@@ -954,15 +1045,15 @@ static void precondition(fvem_hierarchy *h, const double *r, double *z, bool mix
   } else if (mixed) {
     const double sc = rnorm > 0 ? 1.0 / rnorm : 1.0;
     cast_scale(n, r, L0.b32, sc, s);
-    if (h->profiling) ev_record(h->evv, h->evv_used, s);
-    vcycle<float>(h, 0, s);
-    if (h->profiling) ev_record(h->evv, h->evv_used, s);
+    if (h->profile_vcycle) ev_record(h->evv, h->evv_used, s);
+    run_vcycle<float>(h, s);
+    if (h->profile_vcycle) ev_record(h->evv, h->evv_used, s);
     cast_scale(n, L0.x32, z, 1.0 / sc, s);
   } else {
     HIPCHECK(hipMemcpyAsync(L0.b64, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    if (h->profiling) ev_record(h->evv, h->evv_used, s);
-    vcycle<double>(h, 0, s);
-    if (h->profiling) ev_record(h->evv, h->evv_used, s);
+    if (h->profile_vcycle) ev_record(h->evv, h->evv_used, s);
+    run_vcycle<double>(h, s);
+    if (h->profile_vcycle) ev_record(h->evv, h->evv_used, s);
     HIPCHECK(hipMemcpyAsync(z, L0.x64, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   }
   if (h->ncomp0) project_components(n, z, h->comp0, h->ncomp0, h->partial, h->mean, s);
@@ -1008,25 +1099,36 @@ static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const
   HIPCHECK(hipMemcpyAsync(h->r, h->b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   precondition(h, h->r, h->z, mixed, nb, s);
   HIPCHECK(hipMemcpyAsync(h->p, h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  dots_host(h, 1, h->r, h->z, nullptr, nullptr, nullptr, nullptr, d, s);
-  double rz = d[0];
+  // PCG scalars stay on the device: sc[0..1] and sc[4..5] hold (r.z, r.z_old)
+  // of alternate iterations, sc[2] = p.Kp, sc[3] = r.r.  alpha and beta are
+  // formed by the update kernels from them; the host waits once per
+  // iteration, for r.r (the stopping test) together with p.Kp and r.z.
+  double *sc = h->dotout;
+  int cur = 0;   // slot of the current r.z
+  dots(n, 1, h->r, h->z, nullptr, nullptr, nullptr, nullptr, h->partial, sc + cur, s);
   int it = 0;
   double rel = 1.0;
   fvem_status status = FVEM_ERR_NOT_CONVERGED;
   while (it < maxit) {
     spmv<double>(K, h->p, h->q, s);
-    dots_host(h, 1, h->p, h->q, nullptr, nullptr, nullptr, nullptr, d, s);
-    const double pq = d[0];
-    if (!(pq > 0.0) || !std::isfinite(rz)) throw SetupError{FVEM_ERR_NONFINITE, "CG breakdown (p.Kp <= 0)"};
-    const double alpha = rz / pq;
-    pcg_update_xr(n, alpha, h->p, h->q, h->x, h->r, s);
+    dots(n, 1, h->p, h->q, nullptr, nullptr, nullptr, nullptr, h->partial, sc + 2, s);
+    pcg_update_xr(n, sc + cur, sc + 2, h->p, h->q, h->x, h->r, s);
     ++it;
     if (it % m == 0) residual<double>(K, h->x, h->b, h->r, s);
-    dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
+    dots(n, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, h->partial, sc + 3, s);
+    HIPCHECK(hipMemcpyAsync(h->host, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double rz = h->host[cur], pq = h->host[2];
+    if (!(pq > 0.0) || !std::isfinite(rz)) throw SetupError{FVEM_ERR_NONFINITE, "CG breakdown (p.Kp <= 0)"};
+    d[0] = h->host[3];
     rel = std::sqrt(d[0]) / nb;
     if (rel <= tol) {
+      // the true residual decides (slot 6: the r.z slots stay live)
       residual<double>(K, h->x, h->b, h->r, s);
-      dots_host(h, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, d, s);
+      dots(n, 1, h->r, h->r, nullptr, nullptr, nullptr, nullptr, h->partial, sc + 6, s);
+      HIPCHECK(hipMemcpyAsync(h->host + 6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      d[0] = h->host[6];
       rel = std::sqrt(d[0]) / nb;
       if (rel <= tol) {
         status = FVEM_OK;
@@ -1036,10 +1138,11 @@ static fvem_status pcg(fvem_hierarchy *h, const double *bin, double *xout, const
     if (it >= maxit) break;
     std::swap(h->z, h->zold);
     precondition(h, h->r, h->z, mixed, std::sqrt(d[0]), s);
-    dots_host(h, 2, h->r, h->z, h->r, h->zold, nullptr, nullptr, d, s);
-    const double beta = (d[0] - d[1]) / rz;
-    rz = d[0];
-    pcg_update_p(n, h->z, beta, h->p, s);
+    const int nxt = 4 - cur;
+    dots(n, 2, h->r, h->z, h->r, h->zold, nullptr, nullptr, h->partial, sc + nxt, s);
+    // beta = (r.z - r.z_old) / (previous r.z), Polak-Ribiere
+    pcg_update_p(n, h->z, sc + nxt, sc + nxt + 1, sc + cur, h->p, s);
+    cur = nxt;
   }
   if (status != FVEM_OK) {
     residual<double>(K, h->x, h->b, h->r, s);
@@ -1070,7 +1173,8 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
   const bool velocity = vel_op || !so || so->input == FVEM_INPUT_VELOCITY;
   if (velocity && h->nvert == 0) throw SetupError{FVEM_ERR_INVALID, "no divergence operator in this hierarchy"};
   if (vel_op && h->ncell_v == 0) throw SetupError{FVEM_ERR_INVALID, "no velocity operators in this hierarchy"};
-  h->profiling = so && so->profile;
+  h->profiling = so && so->profile == 1;
+  h->profile_vcycle = so && so->profile != 0;
   h->ev_used = 0;
   h->evv_used = 0;
   h->evs_used = 0;
@@ -1136,6 +1240,7 @@ static fvem_status solve_common(fvem_hierarchy *h, const double *in, double *out
     }
   }
   h->profiling = false;
+  h->profile_vcycle = false;
   return stt;
 }
 
@@ -1603,6 +1708,11 @@ void fvem_hierarchy_destroy(fvem_hierarchy *h) {
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->evv) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->evs) (void)hipEventDestroy(e);
+  for (auto &g : h->vg)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (h->gev_in) (void)hipEventDestroy(h->gev_in);
+  if (h->gev_out) (void)hipEventDestroy(h->gev_out);
+  if (h->gstream) (void)hipStreamDestroy(h->gstream);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
 }

@@ -181,6 +181,35 @@ void pcg_update_p(int64_t n, const double *z, double beta, double *p, hipStream_
   if (n) xpby_kernel<<<vgrid(n), 256, 0, s>>>(n, z, beta, p);
 }
 
+// the same updates with alpha = num / den and beta = (num - sub) / den read
+// from device scalars (outputs of the reductions), so that the host need
+// not wait for them
+__global__ void axpy2_dev_kernel(int64_t n, const double *num, const double *den, const double *p, const double *q,
+                                 double *x, double *r) {
+  const double alpha = *num / *den;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+void pcg_update_xr(int64_t n, const double *num, const double *den, const double *p, const double *q, double *x,
+                   double *r, hipStream_t s) {
+  if (n) axpy2_dev_kernel<<<vgrid(n), 256, 0, s>>>(n, num, den, p, q, x, r);
+}
+
+__global__ void xpby_dev_kernel(int64_t n, const double *z, const double *num, const double *sub, const double *den,
+                                double *p) {
+  const double beta = (*num - *sub) / *den;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+void pcg_update_p(int64_t n, const double *z, const double *num, const double *sub, const double *den, double *p,
+                  hipStream_t s) {
+  if (n) xpby_dev_kernel<<<vgrid(n), 256, 0, s>>>(n, z, num, sub, den, p);
+}
+
 template <typename T>
 __global__ void fill_kernel(int64_t n, T *a, T v) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;

@@ -90,6 +90,12 @@ void cast_f64_f32(int64_t n, const double *a, float *b, hipStream_t s);
 void pcg_update_xr(int64_t n, double alpha, const double *p, const double *q, double *x, double *r,
                    hipStream_t s);
 void pcg_update_p(int64_t n, const double *z, double beta, double *p, hipStream_t s);
+// x += a p, r -= a q with a = *num / *den (device scalars)
+void pcg_update_xr(int64_t n, const double *num, const double *den, const double *p, const double *q, double *x,
+                   double *r, hipStream_t s);
+// p = z + b p with b = (*num - *sub) / *den (device scalars)
+void pcg_update_p(int64_t n, const double *z, const double *num, const double *sub, const double *den, double *p,
+                  hipStream_t s);
 template <typename T> void fill(int64_t n, T *a, T v, hipStream_t s);
 
 // deterministic reductions: out[j] = a_j . b_j for j < ndot (ndot <= 3);

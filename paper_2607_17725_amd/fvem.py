@@ -58,7 +58,8 @@ class _Options(ctypes.Structure):
                 ("coarse_dense_max", ctypes.c_int32), ("coarse_rcond", ctypes.c_double),
                 ("coarse_shift", ctypes.c_double), ("small_level_rows", ctypes.c_int64),
                 ("max_templates", ctypes.c_int32), ("lattice_min_fraction", ctypes.c_double),
-                ("column_codes", ctypes.c_int32), ("galerkin_general", ctypes.c_int32)]
+                ("column_codes", ctypes.c_int32), ("galerkin_general", ctypes.c_int32),
+                ("vcycle_graphs", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -201,7 +202,7 @@ class Hierarchy:
 
     def __init__(self, desc, stream=None, cheb_degree=5, cheb_lower=1.0 / 30.0, coarse_dense_max=16384,
                  coarse_rcond=0.0, coarse_shift=1e-8, small_level_rows=0, max_templates=0,
-                 lattice_min_fraction=0.0, galerkin_general=False, column_codes=0):
+                 lattice_min_fraction=0.0, galerkin_general=False, column_codes=0, vcycle_graphs=0):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -211,7 +212,7 @@ class Hierarchy:
             _check(lib.fvem_grid_describe(desc._g, ctypes.byref(g)))
             self._finish(lib, g, [desc], stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond,
                          coarse_shift, small_level_rows, max_templates, lattice_min_fraction, galerkin_general,
-                         column_codes)
+                         column_codes, vcycle_graphs)
             return
         keep = []
         L = len(desc["levels"])
@@ -257,13 +258,16 @@ class Hierarchy:
         g.n_vert = int(desc.get("n_vert", 0))
         g.n_components = int(desc.get("n_components", 0))
         self._finish(lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                     small_level_rows, max_templates, lattice_min_fraction, galerkin_general, column_codes)
+                     small_level_rows, max_templates, lattice_min_fraction, galerkin_general, column_codes,
+                     vcycle_graphs)
 
     def _finish(self, lib, g, keep, stream, cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift,
-                small_level_rows, max_templates, lattice_min_fraction, galerkin_general, column_codes):
+                small_level_rows, max_templates, lattice_min_fraction, galerkin_general, column_codes,
+                vcycle_graphs):
         import torch
         opts = _Options(cheb_degree, cheb_lower, coarse_dense_max, coarse_rcond, coarse_shift, small_level_rows,
-                        max_templates, lattice_min_fraction, int(column_codes), 1 if galerkin_general else 0)
+                        max_templates, lattice_min_fraction, int(column_codes), 1 if galerkin_general else 0,
+                        int(vcycle_graphs))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         _check(lib.fvem_hierarchy_build(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
@@ -291,7 +295,9 @@ class Hierarchy:
         return ctypes.c_void_p(t.data_ptr())
 
     def _opts(self, tol, maxit, precision, input_kind, replace_every, profile):
-        return SolveOpts(tol, maxit, precision, input_kind, replace_every, 1 if profile else 0)
+        # profile: True or 1 times every V-cycle and finest-level launch (kernel by
+        # kernel); 2 times only the V-cycles (graph replays stay on)
+        return SolveOpts(tol, maxit, precision, input_kind, replace_every, int(profile) if profile else 0)
 
     def solve(self, inp, out=None, tol=1e-8, maxit=500, precision=PREC_MIXED, input_kind=INPUT_VELOCITY,
               replace_every=10, profile=False, raise_not_converged=True):

@@ -145,8 +145,9 @@ typedef struct {
     int32_t coarse_dense_max;   /* largest coarsest level factored densely [16384] */
     double coarse_rcond;        /* pivots below rcond * diag are treated as zero [0] */
     double coarse_shift;        /* the coarsest level factors A_c + shift diag(A_c) [1e-8] */
-    int64_t small_level_rows;   /* levels with at most this many rows share each row among 16
-                                   lanes instead of one lane per row [131072]; < 0: never */
+    int64_t small_level_rows;   /* levels (or the sliced rows of a lattice level) with at most
+                                   this many rows share each row among 16 lanes instead of one
+                                   lane per row [400000]; < 0: never */
     int32_t max_templates;      /* value templates per operator [4096]; < 0: none */
     double lattice_min_fraction; /* with dof_lattice: use the lattice stencil layout on a level
                                     below the coarsest when at least this fraction of its rows

@@ -298,7 +298,8 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_template
 // padded level order.  A is in the caller's order; inv maps caller DOF ->
 // level slot.
 static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, HostLattice &lat,
-                                 const std::vector<int32_t> &inv, int max_templates, bool codes, hipStream_t s) {
+                                 const std::vector<int32_t> &inv, int max_templates, bool codes, int64_t small_rows,
+                                 hipStream_t s) {
   std::vector<int32_t> rest;   // caller DOFs of the sliced rows, in level order
   for (int64_t r = 0; r < static_cast<int64_t>(V.order.size()); ++r) {
     const int32_t i = V.order[r];
@@ -312,7 +313,8 @@ static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, 
   for (size_t k = 0; k < ord.size(); ++k) rowmap[k] = inv[rest[ord[k]]];
   V.A.rowmap = h->mem.upload(rowmap, s);
   V.A.hrowmap = std::move(rowmap);
-  V.A.split = false;
+  // the sliced rows share lanes like a small level's when there are few of them
+  V.A.split = small_rows >= 0 && static_cast<int64_t>(ord.size()) <= small_rows;
   V.A.m = V.n;
   auto &st = V.A.st;
   st.ntiles = static_cast<int64_t>(lat.tiles.size());
@@ -495,7 +497,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   const int64_t dense_max = (o && o->coarse_dense_max > 0) ? o->coarse_dense_max : 16384;
   const double rcond = (o && o->coarse_rcond > 0) ? o->coarse_rcond : 0.0;
   const double shift = (o && o->coarse_shift > 0) ? o->coarse_shift : 1e-8;
-  const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 131072;
+  const int64_t small_rows = (o && o->small_level_rows != 0) ? o->small_level_rows : 400000;
   const int max_templates = (o && o->max_templates != 0) ? o->max_templates : 4096;
   const double lattice_min = (o && o->lattice_min_fraction != 0) ? o->lattice_min_fraction : 0.5;
   const bool general = o && o->galerkin_general != 0;
@@ -716,7 +718,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
     int64_t mark = h->mem.bytes;
     if (on_lattice[l]) {
       V.n = static_cast<int64_t>(V.order.size());
-      upload_lattice_level(h, V, A[l], lat[l], inv[l], max_templates, codes, s);
+      upload_lattice_level(h, V, A[l], lat[l], inv[l], max_templates, codes, small_rows, s);
       dinv.assign(V.n, 0.0);
       const HostCSR &Al = A[l];
 #pragma omp parallel for schedule(dynamic, 4096)

@@ -46,6 +46,22 @@ def c4_small():
     return oracle_problem("c4", 8)
 
 
+@pytest.fixture(scope="session")
+def c1_16():
+    """c1 at its named size, 16^3 (k = 1, Dirichlet top)."""
+    return oracle_problem("c1", 16)
+
+
+@pytest.fixture(scope="session")
+def c3_16():
+    return oracle_problem("c3", 16)
+
+
+@pytest.fixture(scope="session")
+def c4_16():
+    return oracle_problem("c4", 16)
+
+
 @pytest.fixture
 def rng():
     return np.random.default_rng(1234)

@@ -34,6 +34,8 @@ def log(msg):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_cheb_plates128_traffic.json")
+# iteration cap of the benchmark's solves (the thin sheet needs several hundred)
+MAXIT = 2000
 # the stencil kernel, its epilogue and view, and the host code that lays the
 # lattice tiles out
 LAYOUT_SOURCES = [os.path.join(ROOT, "paper_2607_17725_amd", "csrc", f)
@@ -261,7 +263,7 @@ def main():
     def step(profile):
         st_all = []
         for u in U:
-            _, st = hier.solve(u, out=p, tol=w.tol, precision=prec, profile=profile)
+            _, st = hier.solve(u, out=p, tol=w.tol, precision=prec, profile=profile, maxit=MAXIT)
             st_all.append(st)
         return st_all
 
@@ -287,7 +289,7 @@ def main():
     # (profile level 1, V-cycles kernel by kernel)
     kstats = []
     for u in U[:min(len(U), 2)]:
-        kstats.append(hier.solve(u, out=p, tol=w.tol, precision=prec, profile=1)[1])
+        kstats.append(hier.solve(u, out=p, tol=w.tol, precision=prec, profile=1, maxit=MAXIT)[1])
     ms_k = sum(s["ms_fine_smoother"] for s in kstats)
     n_k = sum(s["n_fine_smoother"] for s in kstats)
     avg_ms = ms_k / max(n_k, 1)
@@ -296,11 +298,11 @@ def main():
     ms_s = sum(s["ms_fine_stencil"] for s in kstats)
     n_s = sum(s["n_fine_stencil"] for s in kstats)
     st0 = hier.level_stencil(0)
-    # algorithmic bytes of one stencil launch: six FP32 vector streams per
-    # stencil row (x, b, D^-1, d read; d, x_out written) and a tile id plus 8
-    # mask words per tile; the class tables and halo re-reads of x are cache
-    # traffic and are not counted
-    st_bytes = 24 * st0["rows"] + 68 * st0["tiles"]
+    # algorithmic bytes of one stencil launch: five FP32 vector streams per
+    # stencil row (x, b, d read; d, x_out written; D^-1 is the class's) and a
+    # tile id plus 8 mask words per tile; the class tables and halo re-reads
+    # of x are cache traffic and are not counted
+    st_bytes = 20 * st0["rows"] + 68 * st0["tiles"]
     st_ms = ms_s / max(n_s, 1)
     st_gbs = st_bytes / (st_ms * 1e-3) / 1e9 if n_s else 0.0
     # whole V-cycles (all levels, transfers and the coarsest solve), timed
@@ -314,11 +316,12 @@ def main():
     # (a 16-bit column code per nonzero of coded slices plus their block
     # tables, an int32 column per nonzero elsewhere; an FP32 value per
     # nonzero of rows that store values; an int32 template id per row that
-    # reads a shared value template) and six FP32 vector streams (x, b, D^-1,
-    # d read; d, x_out written); slice padding, the cache-resident template
-    # table and cache misses are not counted
+    # reads a shared value template) and six FP32 vector streams per row (x,
+    # b, D^-1, d read; d, x_out written; stencil rows take D^-1 from their
+    # class); slice padding, the cache-resident template table and cache
+    # misses are not counted
     matrix_bytes = hier.level_bytes(0, fvem.PREC_MIXED)
-    bytes_per_launch = matrix_bytes + 24 * n0
+    bytes_per_launch = matrix_bytes + 24 * n0 - 4 * st0["rows"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     log(f"{solves} solves in {dt:.2f} s: {value:.3f} solves/s, iterations {min(its)}-{max(its)}, "
         f"max residual {max(res):.2e}; fine Chebyshev step {avg_ms:.3f} ms avg over {n_k} launches "
@@ -333,7 +336,7 @@ def main():
         # sensitivity) in the benchmark's precision, both to the same tolerance
         prec_save = prec
         prec = fvem.PREC_FP64
-        hier.solve(U[0], out=p, tol=w.tol, precision=prec)   # untimed: captures the FP64 V-cycle graphs
+        hier.solve(U[0], out=p, tol=w.tol, precision=prec, maxit=MAXIT)   # untimed: captures the FP64 graphs
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         st64 = step(False)
@@ -344,12 +347,28 @@ def main():
                                    "iterations": [s["iterations"] for s in st64],
                                    "max_rel_residual": max(s["rel_residual"] for s in st64)}
         log(f"FP64 reference: {len(U) / d64:.3f} solves/s")
+        # error of the mixed-precision pressure against the FP64 one on the
+        # first right-hand sides (untimed), at the benchmark tolerance and, for
+        # cache-resident sizes, also at 1e-10
+        tols = [w.tol] + ([1e-10] if n0 <= 2_000_000 and w.tol > 1e-10 else [])
+        p64 = torch.empty_like(p)
+        errs = []
+        for tol in tols:
+            for u in U[:2]:
+                _, sm = hier.solve(u, out=p, tol=tol, precision=fvem.PREC_MIXED, maxit=MAXIT)
+                _, sd = hier.solve(u, out=p64, tol=tol, precision=fvem.PREC_FP64, maxit=MAXIT)
+                rel = float(torch.linalg.vector_norm(p - p64) / torch.linalg.vector_norm(p64))
+                errs.append({"tol": tol, "iterations_mixed": sm["iterations"], "iterations_fp64": sd["iterations"],
+                             "rel_l2_mixed_vs_fp64": rel})
+                log(f"tol {tol:g}: mixed {sm['iterations']} its, FP64 {sd['iterations']} its, "
+                    f"|p_mixed - p_fp64| / |p_fp64| = {rel:.2e}")
+        extra["fp64_reference"]["error_table"] = errs
         G = [torch.as_tensor(np.random.default_rng(500 + k).standard_normal(n0), device="cuda")
              for k in range(len(U))]
         gu = torch.empty(3 * grid.n_vert, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        sta = [hier.solve_adjoint(gp, out=gu, tol=w.tol, precision=prec)[1] for gp in G]
+        sta = [hier.solve_adjoint(gp, out=gu, tol=w.tol, precision=prec, maxit=MAXIT)[1] for gp in G]
         torch.cuda.synchronize()
         dad = time.perf_counter() - t1
         extra["adjoint"] = {"solves_per_s": len(G) / dad, "iterations": [s["iterations"] for s in sta],

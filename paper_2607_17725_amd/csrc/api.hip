@@ -105,8 +105,8 @@ struct DevSELL {
     int64_t ntiles = 0, n_rows = 0, nnz = 0;
     int32_t *tiles = nullptr, *tile_base = nullptr, *len = nullptr, *off = nullptr;
     uint64_t *mask = nullptr;
-    double *val64 = nullptr;
-    float *val32 = nullptr;
+    double *val64 = nullptr, *dinv64 = nullptr;
+    float *val32 = nullptr, *dinv32 = nullptr;
     int32_t tn = 0, lat_n = 0;
     bool standard = false;          // every class has the full order-2 support
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // set while the stencil launch is timed
@@ -114,14 +114,14 @@ struct DevSELL {
   } st;
   DevSELLView<double> d() const {
     DevSELLView<double> v{n, m, nslices, sl, cp, ci, bt, c16, btab, d64.vp, v64, d64.tid, tv64, d64.tw, split, rowmap};
-    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val64, st.standard,
-            st.ev0, st.ev1};
+    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val64, st.dinv64,
+            st.standard, st.ev0, st.ev1};
     return v;
   }
   DevSELLView<float> f() const {
     DevSELLView<float> v{n, m, nslices, sl, cp, ci, bt, c16, btab, d32.vp, v32, d32.tid, tv32, d32.tw, split, rowmap};
-    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val32, st.standard,
-            st.ev0, st.ev1};
+    v.st = {st.ntiles, st.tiles, st.mask, st.tile_base, st.tn, st.lat_n, st.len, st.off, st.val32, st.dinv32,
+            st.standard, st.ev0, st.ev1};
     return v;
   }
 };
@@ -343,6 +343,17 @@ static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, 
   }
   st.val32 = h->mem.alloc<float>(static_cast<int64_t>(lat.val.size()));
   cast_f64_f32(static_cast<int64_t>(lat.val.size()), st.val64, st.val32, s);
+  {
+    // every stencil row of a class has the class's diagonal (offset code 62:
+    // zero offset), so its D^-1 is the class's: 1 / a_ii as for the vector
+    std::vector<double> dv(8, 0.0);
+    for (int t = 0; t < 8; ++t)
+      for (int j = 0; j < lat.len[t]; ++j)
+        if (lat.delta[128 * t + j] == 62 && lat.val[128 * t + j] > 0.0) dv[t] = 1.0 / lat.val[128 * t + j];
+    st.dinv64 = h->mem.upload(dv, s);
+    st.dinv32 = h->mem.alloc<float>(8);
+    cast_f64_f32(8, st.dinv64, st.dinv32, s);
+  }
   HIPCHECK(hipStreamSynchronize(s));
   lat.order.clear();
   lat.order.shrink_to_fit();
@@ -1456,6 +1467,7 @@ fvem_status fvem_vcycle_bytes(fvem_hierarchy *h, int32_t precision, int64_t *byt
     // x read and written)
     total += 2 * deg * sell_bytes(L.A, precision) + sell_bytes(L.R, precision) + sell_bytes(L.P, precision);
     total += s * (n * (4 + 6 * (2 * deg - 1) + 3 + 1 + 2) + 2 * nn);
+    total -= s * (2 * deg - 1) * L.A.st.n_rows;   // stencil rows take D^-1 from their class
   }
   // coarsest: the dense generalised inverse, read once, and its vectors
   total += 8 * h->nc * h->nc + (s + 8) * 2 * h->nc;

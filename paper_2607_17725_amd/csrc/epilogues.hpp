@@ -12,6 +12,9 @@ namespace fvem {
 // Each epilogue can also be split in two for kernels that overlap the
 // row's own vector reads with their gathers: pre(i) issues the reads,
 // apply(i, a, pre, x_i) finishes the row given x_i (x at the row itself).
+// Lattice stencil rows share their class's diagonal, so the Chebyshev step
+// takes D^-1 from the class there: pre_s / apply_s(..., dinv) skip its
+// stream (the other epilogues do not read D^-1 and alias them).
 
 template <typename T>
 struct EpiStore {
@@ -21,6 +24,9 @@ struct EpiStore {
   struct Pre {};
   __device__ Pre pre(int64_t) const { return {}; }
   __device__ void apply(int64_t i, T a, const Pre &, T) const { y[i] = a; }
+  using PreS = Pre;
+  __device__ PreS pre_s(int64_t i) const { return pre(i); }
+  __device__ void apply_s(int64_t i, T a, const PreS &p, T x, T) const { apply(i, a, p, x); }
 };
 
 template <typename T>
@@ -32,6 +38,9 @@ struct EpiResidual {  // y = b - A x
   struct Pre { T b; };
   __device__ Pre pre(int64_t i) const { return {b[i]}; }
   __device__ void apply(int64_t i, T a, const Pre &p, T) const { y[i] = p.b - a; }
+  using PreS = Pre;
+  __device__ PreS pre_s(int64_t i) const { return pre(i); }
+  __device__ void apply_s(int64_t i, T a, const PreS &p, T x, T) const { apply(i, a, p, x); }
 };
 
 template <typename T>
@@ -42,6 +51,9 @@ struct EpiAdd {  // y += A x  (prolong-and-correct)
   struct Pre { T y; };
   __device__ Pre pre(int64_t i) const { return {y[i]}; }
   __device__ void apply(int64_t i, T a, const Pre &p, T) const { y[i] = p.y + a; }
+  using PreS = Pre;
+  __device__ PreS pre_s(int64_t i) const { return pre(i); }
+  __device__ void apply_s(int64_t i, T a, const PreS &p, T x, T) const { apply(i, a, p, x); }
 };
 
 struct EpiScaled {  // y = alpha A x
@@ -66,6 +78,13 @@ struct EpiCheb {  // d = ca d + cb dinv (b - A xin);  xout = xin + d
   __device__ Pre pre(int64_t i) const { return {b[i], dinv[i], d[i]}; }
   __device__ void apply(int64_t i, T a, const Pre &p, T x) const {
     const T dn = ca * p.d + cb * p.dinv * (p.b - a);
+    d[i] = dn;
+    xout[i] = x + dn;
+  }
+  struct PreS { T b, d; };
+  __device__ PreS pre_s(int64_t i) const { return {b[i], d[i]}; }
+  __device__ void apply_s(int64_t i, T a, const PreS &p, T x, T dv) const {
+    const T dn = ca * p.d + cb * dv * (p.b - a);
     d[i] = dn;
     xout[i] = x + dn;
   }

@@ -31,6 +31,7 @@ struct StencilView {
   const int32_t *len = nullptr;        // 8 entry counts
   const int32_t *off = nullptr;        // 8 x 128 LDS offsets
   const T *val = nullptr;              // 8 x 128 values
+  const T *dinv = nullptr;             // 8: 1 / (diagonal of each class's stencil)
   bool standard = false;               // every class has the full order-2 support (unrolled kernel)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;   // recorded around the stencil launch when set
 };

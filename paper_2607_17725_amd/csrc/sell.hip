@@ -273,8 +273,8 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const 
   const int lane = threadIdx.x & 63;
   const bool active = (st.mask[8 * b + t] >> lane) & 1;
   const int64_t row = static_cast<int64_t>(nbase[13]) + 64 * t + lane;
-  typename Epi::Pre pre{};
-  if (active) pre = epi.pre(row);
+  typename Epi::PreS pre{};
+  if (active) pre = epi.pre_s(row);
   // 1728 halo values, at most 4 per thread, issued before any is used
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const 
   }
   // x at the row itself: class t's sub-grid, one point inside the halo along each axis
   const XT xi = hp[t * STENCIL_SUB + STENCIL_P1 + STENCIL_P2 + 1];
-  epi.apply(row, acc, pre, static_cast<AT>(xi));
+  epi.apply_s(row, acc, pre, static_cast<AT>(xi), static_cast<AT>(st.dinv[t]));
 }
 
 template <typename VT, typename XT, class Epi>

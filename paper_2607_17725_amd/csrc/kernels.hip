@@ -503,50 +503,99 @@ __global__ __launch_bounds__(256) void trsm_panel_kernel(double *A, int64_t ld, 
   for (int j = 0; j < nb; ++j) A[row + (k0 + j) * ld] = x[j];
 }
 
-// C[m0.., n0..] (+)= alpha * op(A) op(B), MFMA f64 16x16x4.  op(A)(i,k) =
-// A[i*sai + k*sak], op(B)(k,j) = B[k*sbk + j*sbj], C column-major (ldc).
-// One wave computes a 16x16 tile; a block of 4 waves covers 32x32.
-// Only tiles with tile_row >= tile_col are computed when lower_only is set.
+// C (+)= alpha op(A) op(B) on FP64 MFMA (v_mfma_f64_16x16x4f64), with
+// op(A)(i,k) = A[i*sai + k*sak], op(B)(k,j) = B[k*sbk + j*sbj] and C
+// column-major (ldc).  A workgroup of 4 wavefronts computes a 64 x 64 block
+// of C; wavefront w owns the 32 x 32 quarter (w & 1, w >> 1) as 2 x 2 MFMA
+// tiles.  K is walked in chunks of 16: both operands' 64 x 16 panels are
+// staged in LDS, k-major, so a block reads each global element once per
+// chunk (8 flop per byte from L2 instead of 2 with per-tile loads).  With
+// lower_only, blocks wholly above the diagonal are skipped; the blocks that
+// straddle it are computed whole.
 typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int GEMM_B = 64, GEMM_K = 16;
+// LDS row pitch: 80 doubles puts consecutive k rows 32 banks apart, so the
+// two k rows read by each half-wavefront fall on distinct banks
+constexpr int GEMM_PITCH = GEMM_B + 16;
 
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                        const double *A, int64_t sai, int64_t sak,
                                                        const double *B, int64_t sbk, int64_t sbj, double beta,
                                                        double *C, int64_t ldc, int lower_only) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t i0 = (static_cast<int64_t>(blockIdx.x) * 2 + (wave & 1)) * 16;
-  const int64_t j0 = (static_cast<int64_t>(blockIdx.y) * 2 + (wave >> 1)) * 16;
-  if (i0 >= M || j0 >= N) return;
-  if (lower_only && i0 + 15 < j0) return;
-  const int r = lane & 15;   // row of A / column of B
-  const int kk = lane >> 4;  // k within the 4-step
-  double4_t acc = {0.0, 0.0, 0.0, 0.0};
-  const int64_t ia = i0 + r, jb = j0 + r;
-  for (int64_t k = 0; k < K; k += 4) {
-    const int64_t kc = k + kk;
-    const double a = (ia < M && kc < K) ? A[ia * sai + kc * sak] : 0.0;
-    const double b = (jb < N && kc < K) ? B[kc * sbk + jb * sbj] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-  // D layout (measured on gfx950): register q of a lane holds row
-  // (lane / 16) + 4 q, column lane % 16; A and B are row-of-lane / k-of-group
+  __shared__ double As[GEMM_K * GEMM_PITCH];
+  __shared__ double Bs[GEMM_K * GEMM_PITCH];
+  const int64_t ib = static_cast<int64_t>(blockIdx.x) * GEMM_B;
+  const int64_t jb = static_cast<int64_t>(blockIdx.y) * GEMM_B;
+  if (lower_only && ib + GEMM_B - 1 < jb) return;   // whole workgroup
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int r = lane & 15;   // row of A / column of B inside a 16 x 16 tile
+  const int kk = lane >> 4;  // k inside a 4-step
+  // panel loads run along whichever index is contiguous in memory
+  const bool a_i_fast = sai == 1, b_j_fast = sbj == 1;
+  double4_t acc[2][2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t i = i0 + (lane >> 4) + 4 * q;
-    const int64_t j = j0 + (lane & 15);
-    if (i < M && j < N) {
-      double *c = C + i + j * ldc;
-      *c = alpha * acc[q] + (beta == 0.0 ? 0.0 : beta * *c);
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) acc[m][n] = double4_t{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kb = 0; kb < K; kb += GEMM_K) {
+    double va[4], vb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int ia = a_i_fast ? (e & 63) : (e >> 4), ka = a_i_fast ? (e >> 6) : (e & 15);
+      const int jb_ = b_j_fast ? (e & 63) : (e >> 4), kb_ = b_j_fast ? (e >> 6) : (e & 15);
+      const int64_t gi = ib + ia, gka = kb + ka, gj = jb + jb_, gkb = kb + kb_;
+      va[q] = (gi < M && gka < K) ? A[gi * sai + gka * sak] : 0.0;
+      vb[q] = (gj < N && gkb < K) ? B[gkb * sbk + gj * sbj] : 0.0;
+    }
+    __syncthreads();   // the previous chunk's reads of As and Bs are done
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int ia = a_i_fast ? (e & 63) : (e >> 4), ka = a_i_fast ? (e >> 6) : (e & 15);
+      const int jb_ = b_j_fast ? (e & 63) : (e >> 4), kb_ = b_j_fast ? (e >> 6) : (e & 15);
+      As[ka * GEMM_PITCH + ia] = va[q];
+      Bs[kb_ * GEMM_PITCH + jb_] = vb[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GEMM_K; ks += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) a[m] = As[(ks + kk) * GEMM_PITCH + wr + 16 * m + r];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) b[n] = Bs[(ks + kk) * GEMM_PITCH + wc + 16 * n + r];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
     }
   }
+  // D layout (measured on gfx950): register q of a lane holds row
+  // (lane / 16) + 4 q, column lane % 16 of its 16 x 16 tile
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t i = ib + wr + 16 * m + (lane >> 4) + 4 * q;
+        const int64_t j = jb + wc + 16 * n + (lane & 15);
+        if (i < M && j < N) {
+          double *c = C + i + j * ldc;
+          *c = alpha * acc[m][n][q] + (beta == 0.0 ? 0.0 : beta * *c);
+        }
+      }
 }
 
 void gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t sai, int64_t sak,
               const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc, bool lower_only,
               hipStream_t s) {
   if (M <= 0 || N <= 0) return;
-  const dim3 g(static_cast<unsigned>((M + 31) / 32), static_cast<unsigned>((N + 31) / 32));
+  const dim3 g(static_cast<unsigned>((M + GEMM_B - 1) / GEMM_B), static_cast<unsigned>((N + GEMM_B - 1) / GEMM_B));
   gemm_f64_kernel<<<g, 256, 0, s>>>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc, lower_only ? 1 : 0);
 }
 

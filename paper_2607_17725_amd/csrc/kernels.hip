@@ -298,40 +298,77 @@ void dots(int64_t n, int ndot, const double *a0, const double *b0, const double 
 // Per-component sums and counts of one block's contiguous chunk: every
 // thread accumulates its strided elements into its own LDS slot per
 // component, then the slots are combined by a fixed-order tree, so the
-// result is independent of scheduling.
+// result is independent of scheduling.  A thread keeps the slot of its
+// current component in registers while consecutive elements stay in that
+// component (the level order is spatial, so runs are long) and reads its
+// elements four strides ahead; the additions into each slot are the same
+// sequence as element-by-element LDS updates.  The slots take 4 KiB of LDS
+// per component of the pass, so a one-component domain does not limit the
+// blocks per CU.
 constexpr int COMP_CHUNK = 16;
 
 __global__ __launch_bounds__(256) void comp_partial_kernel(int64_t n, const double *v, const int32_t *comp,
                                                            int c0, int nc, double *partial) {
-  __shared__ double s_sum[COMP_CHUNK][256];
-  __shared__ double s_cnt[COMP_CHUNK][256];
+  extern __shared__ double slots[];   // nc sums, then nc counts, 256 per component
+  double *s_sum = slots, *s_cnt = slots + 256 * nc;
   const int t = threadIdx.x;
   for (int j = 0; j < nc; ++j) {
-    s_sum[j][t] = 0.0;
-    s_cnt[j][t] = 0.0;
+    s_sum[256 * j + t] = 0.0;
+    s_cnt[256 * j + t] = 0.0;
   }
   const int64_t per_block = (n + REDUCE_BLOCKS - 1) / REDUCE_BLOCKS;
   const int64_t lo = blockIdx.x * per_block;
   const int64_t hi = lo + per_block < n ? lo + per_block : n;
-  for (int64_t i = lo + t; i < hi; i += 256) {
-    const int c = comp[i] - c0;
-    if (c >= 0 && c < nc) {
-      s_sum[c][t] += v[i];
-      s_cnt[c][t] += 1.0;
+  int cur = -1;   // component held in (acc, cnt); -1: none
+  double acc = 0.0, cnt = 0.0;
+  for (int64_t i0 = lo + t; i0 < hi; i0 += 4 * 256) {
+    int cc[4];
+    double vv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = i0 + 256 * q;
+      cc[q] = -1;
+      vv[q] = 0.0;
+      if (i < hi) {
+        const int c = comp[i] - c0;
+        if (c >= 0 && c < nc) {
+          cc[q] = c;
+          vv[q] = v[i];
+        }
+      }
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (cc[q] < 0) continue;
+      if (cc[q] != cur) {
+        if (cur >= 0) {
+          s_sum[256 * cur + t] = acc;
+          s_cnt[256 * cur + t] = cnt;
+        }
+        cur = cc[q];
+        acc = s_sum[256 * cur + t];
+        cnt = s_cnt[256 * cur + t];
+      }
+      acc += vv[q];
+      cnt += 1.0;
+    }
+  }
+  if (cur >= 0) {
+    s_sum[256 * cur + t] = acc;
+    s_cnt[256 * cur + t] = cnt;
   }
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (t < o)
       for (int j = 0; j < nc; ++j) {
-        s_sum[j][t] += s_sum[j][t + o];
-        s_cnt[j][t] += s_cnt[j][t + o];
+        s_sum[256 * j + t] += s_sum[256 * j + t + o];
+        s_cnt[256 * j + t] += s_cnt[256 * j + t + o];
       }
     __syncthreads();
   }
   if (t < nc) {
-    partial[(2 * t) * REDUCE_BLOCKS + blockIdx.x] = s_sum[t][0];
-    partial[(2 * t + 1) * REDUCE_BLOCKS + blockIdx.x] = s_cnt[t][0];
+    partial[(2 * t) * REDUCE_BLOCKS + blockIdx.x] = s_sum[256 * t];
+    partial[(2 * t + 1) * REDUCE_BLOCKS + blockIdx.x] = s_cnt[256 * t];
   }
 }
 
@@ -368,7 +405,7 @@ void project_components(int64_t n, double *v, const int32_t *comp, int n_comp, d
                         hipStream_t s) {
   for (int c0 = 0; c0 < n_comp; c0 += COMP_CHUNK) {
     const int nc = n_comp - c0 < COMP_CHUNK ? n_comp - c0 : COMP_CHUNK;
-    comp_partial_kernel<<<REDUCE_BLOCKS, 256, 0, s>>>(n, v, comp, c0, nc, partial);
+    comp_partial_kernel<<<REDUCE_BLOCKS, 256, 2 * 256 * nc * sizeof(double), s>>>(n, v, comp, c0, nc, partial);
     comp_final_kernel<<<nc, 256, 0, s>>>(nc, partial, mean);
     comp_sub_kernel<<<vgrid(n), 256, 0, s>>>(n, v, comp, c0, nc, mean);
   }

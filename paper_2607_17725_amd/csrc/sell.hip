@@ -218,62 +218,71 @@ __global__ __launch_bounds__(256) void sell_split_kernel(
   if (k == 0) epi(rowmap ? static_cast<int64_t>(rowmap[row]) : row, acc);
 }
 
-// Lattice stencil rows.  One workgroup of 8 wavefronts per tile; wavefront
-// t handles the 64 slots of class t.  The tile's 8^3 points plus a 2-point
-// halo (12^3 = 1728 values) are staged in LDS, split by class into 6^3
-// sub-grids whose pitches (8 per row, 68 per plane) keep the 32 lanes of a
-// half-wavefront on distinct banks.  The class table (LDS offset, value) is
-// wave-uniform, so its entries come through scalar loads; every lane sums its
-// entries in the table's fixed order (deterministic).
+// Lattice stencil rows.  A tile's 8^3 points plus a 2-point halo (12^3 =
+// 1728 values) are staged in LDS, split by class into 6^3 sub-grids with
+// pitches of 8 per row and 68 per plane.  The class table (LDS offset,
+// value) is wave-uniform, so its entries come through scalar loads; every
+// row sums its entries in the table's fixed order (deterministic).
 // Rows of class T = 4 ta + 2 tb + tc with the standard order-2 support:
 // offsets in [-2, 2] along even coordinates and [-1, 1] along odd ones, in
 // the table's order (increasing offset code).  Offsets and LDS addresses are
-// compile-time constants; the values come from the wave-uniform table.
-template <int T, int NT, typename VT, typename XT, typename AT>
-__device__ __forceinline__ void stencil_rows_std(const XT *hp, const VT *val, AT acc[NT]) {
+// compile-time constants; the values come from the table.
+// Each lane sums two rows of class T, neighbours along b (sub-grid rows pj
+// and pj + 1 of one tile): the lattice offsets db of the first row and
+// db - 2 of the second share their x values, so each value of the union
+// [-rb, rb + 2] is read from LDS once (a quarter fewer reads than one row
+// per lane).  Each row still adds its entries in the table's order, so the
+// sums equal those of one row per lane.  The 32 lanes of a half-wavefront
+// (4 planes, 2 row pairs, 4 columns) fall on distinct banks.  hp is the
+// first row's base in the lane's first tile; its tiles are TS apart in LDS.
+template <int T, int NL, int TS, typename VT, typename XT, typename AT>
+__device__ __forceinline__ void stencil_pairs_std(const XT *hp, const VT *val, AT acc[NL][2]) {
   constexpr int ta = T >> 2, tb = (T >> 1) & 1, tc = T & 1;
   constexpr int ra = ta ? 1 : 2, rb = tb ? 1 : 2, rc = tc ? 1 : 2;
+  constexpr int nb = 2 * rb + 1, nc = 2 * rc + 1;
 #pragma unroll
-  for (int u = 0; u < NT; ++u) acc[u] = 0;
-  int j = 0;
+  for (int v = 0; v < NL; ++v) acc[v][0] = acc[v][1] = 0;
 #pragma unroll
   for (int da = -ra; da <= ra; ++da)
 #pragma unroll
-    for (int db = -rb; db <= rb; ++db)
+    for (int e = -rb; e <= rb + 2; ++e)
 #pragma unroll
       for (int dc = -rc; dc <= rc; ++dc) {
-        const int ua = (ta + da) & 1, ub = (tb + db) & 1, uc = (tc + dc) & 1;
+        const int ua = (ta + da) & 1, ub = (tb + e) & 1, uc = (tc + dc) & 1;
         const int off = (4 * ua + 2 * ub + uc) * STENCIL_SUB + ((ta + da + 2 - ua) / 2) * STENCIL_P1 +
-                        ((tb + db + 2 - ub) / 2) * STENCIL_P2 + (tc + dc + 2 - uc) / 2;
-        const AT v = static_cast<AT>(val[j]);
+                        ((tb + e + 2 - ub) / 2) * STENCIL_P2 + (tc + dc + 2 - uc) / 2;
+        const int j0 = ((da + ra) * nb + (e + rb)) * nc + (dc + rc);       // first row, db = e
+        const int j1 = ((da + ra) * nb + (e - 2 + rb)) * nc + (dc + rc);   // second row, db = e - 2
 #pragma unroll
-        for (int u = 0; u < NT; ++u) acc[u] += v * static_cast<AT>(hp[u * 8 * STENCIL_SUB + off]);
-        ++j;
+        for (int v = 0; v < NL; ++v) {
+          const AT xv = static_cast<AT>(hp[v * TS + off]);
+          if (e <= rb) acc[v][0] += static_cast<AT>(val[j0]) * xv;
+          if (e - 2 >= -rb) acc[v][1] += static_cast<AT>(val[j1]) * xv;
+        }
       }
 }
 
-// Tiles per stencil workgroup.  The tiles of one workgroup share its latency
-// chain (tile ids, neighbour bases, the barriers) and its class tables, and
-// each lane sums the rows of its slot in every tile together, so a
-// workgroup keeps several tiles' loads in flight where one tile's would
-// leave the CU waiting.  Measured on the 128^3 plates (FP32 Chebyshev
-// step): 1, 2, 3, 4 tiles take 0.247, 0.201, 0.190, 0.223 ms; with 3 the
-// FP32 halos take 39 KB of LDS, four workgroups per CU.
-constexpr int STENCIL_TPW = 3;
+// Tiles per stencil workgroup (even: a half-wavefront takes every other
+// tile).  The tiles of one workgroup share its latency chain (tile ids,
+// neighbour bases, the barriers) and its class tables.  Measured on the
+// 128^3 plates (FP32 Chebyshev step): with one row per lane, 1, 2, 3, 4
+// tiles took 0.247, 0.201, 0.190, 0.223 ms; with two rows per lane, 2, 4, 6
+// tiles take 0.164, 0.169, 0.203 ms.
+constexpr int STENCIL_TPW = 2;
 
-// One workgroup of 8 wavefronts per STENCIL_TPW consecutive tiles; wavefront
-// t handles the 64 slots of class t in each of them.  Every tile's 8^3
-// points plus a 2-point halo (12^3 values) are staged in LDS, split by class
-// into 6^3 sub-grids.
+// One workgroup of 8 wavefronts per STENCIL_TPW consecutive tiles;
+// wavefront t handles the slots of class t.  Every tile's 8^3 points plus a
+// 2-point halo (12^3 values) are staged in LDS, split by class into 6^3
+// sub-grids; each lane then sums two rows of its class (sub-grid rows pj and
+// pj + 1) per tile of its half-wavefront.
 template <typename VT, typename XT, class Epi>
 __global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const XT *__restrict__ x, Epi epi) {
-  constexpr int NT = STENCIL_TPW;
-  __shared__ XT halo[NT * 8 * STENCIL_SUB];
-  __shared__ int32_t nbase[NT][27];   // slot bases of each tile and its 26 neighbours (-1: none)
+  constexpr int NT = STENCIL_TPW, NL = NT / 2, TILE = 8 * STENCIL_SUB;
+  __shared__ XT halo[NT * TILE];
+  __shared__ int32_t nbase[NT][27];
   const int64_t b0 = NT * xcd_contiguous(blockIdx.x, gridDim.x);
-  const int nt = static_cast<int>(min(static_cast<int64_t>(NT), st.ntiles - b0));   // >= 1
+  const int nt = static_cast<int>(min(static_cast<int64_t>(NT), st.ntiles - b0));
   const int tn = st.tn, N = st.lat_n;
-  // threads 32 u + j (j < 27) fetch neighbour j of tile u
   if (threadIdx.x < 32 * NT) {
     const int u = threadIdx.x >> 5, j = threadIdx.x & 31;
     if (j < 27 && u < nt) {
@@ -285,22 +294,29 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const 
     }
   }
   __syncthreads();
-  // the rows' own vector reads go out with the halo gathers
   const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  bool active[NT];
-  int64_t row[NT];
-  typename Epi::PreS pre[NT];
+  // half-wavefront h takes tiles h, h + 2, ...; its 32 lanes the pairs of
+  // sub-grid rows (pi, 2 pjp) and (pi, 2 pjp + 1) at column pk
+  const int h = lane >> 5, m = lane & 31;
+  const int pi = m >> 3, pjp = (m >> 2) & 1, pk = m & 3;
+  const int pos = 16 * pi + 8 * pjp + pk;   // the second row is pos + 4
+  bool active[NL][2];
+  int64_t row[NL][2];
+  typename Epi::PreS pre[NL][2];
   bool any = false;
 #pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    active[u] = u < nt && ((st.mask[8 * (b0 + u) + t] >> lane) & 1);
-    row[u] = u < nt ? static_cast<int64_t>(nbase[u][13]) + 64 * t + lane : 0;
-    pre[u] = {};
-    if (active[u]) pre[u] = epi.pre_s(row[u]);
-    any = any || active[u];
+  for (int v = 0; v < NL; ++v) {
+    const int u = h + 2 * v;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      active[v][r] = u < nt && ((st.mask[8 * (b0 + u) + t] >> (pos + 4 * r)) & 1);
+      row[v][r] = u < nt ? static_cast<int64_t>(nbase[u][13]) + 64 * t + pos + 4 * r : 0;
+      pre[v][r] = {};
+      if (active[v][r]) pre[v][r] = epi.pre_s(row[v][r]);
+      any = any || active[v][r];
+    }
   }
-  // 1728 halo values per tile, at most 4 per thread, all issued before any is used
   XT hv[NT][4];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
@@ -331,48 +347,48 @@ __global__ __launch_bounds__(512) void stencil_kernel(StencilView<VT> st, const 
       const int e = threadIdx.x + 512 * q;
       if (e >= 1728) break;
       const int tp = e / 216, r = e - 216 * tp;
-      halo[u * 8 * STENCIL_SUB + tp * STENCIL_SUB + (r / 36) * STENCIL_P1 + ((r / 6) % 6) * STENCIL_P2 + r % 6] =
-          hv[u][q];
+      halo[u * TILE + tp * STENCIL_SUB + (r / 36) * STENCIL_P1 + ((r / 6) % 6) * STENCIL_P2 + r % 6] = hv[u][q];
     }
   }
   __syncthreads();
   if (!any) return;
-  // a lane sums its slot in every tile; the sums of tiles past nt read LDS
-  // that was not filled and are discarded
-  const XT *hp = halo + (lane >> 4) * STENCIL_P1 + ((lane >> 2) & 3) * STENCIL_P2 + (lane & 3);
+  const XT *hp = halo + h * TILE + pi * STENCIL_P1 + 2 * pjp * STENCIL_P2 + pk;
   const VT *val = st.val + 128 * t;
   using AT = typename Epi::acc_t;
-  AT acc[NT];
+  AT acc[NL][2];
   if (st.standard) {
     switch (t) {
-      case 0: stencil_rows_std<0, NT, VT, XT, AT>(hp, val, acc); break;
-      case 1: stencil_rows_std<1, NT, VT, XT, AT>(hp, val, acc); break;
-      case 2: stencil_rows_std<2, NT, VT, XT, AT>(hp, val, acc); break;
-      case 3: stencil_rows_std<3, NT, VT, XT, AT>(hp, val, acc); break;
-      case 4: stencil_rows_std<4, NT, VT, XT, AT>(hp, val, acc); break;
-      case 5: stencil_rows_std<5, NT, VT, XT, AT>(hp, val, acc); break;
-      case 6: stencil_rows_std<6, NT, VT, XT, AT>(hp, val, acc); break;
-      default: stencil_rows_std<7, NT, VT, XT, AT>(hp, val, acc); break;
+      case 0: stencil_pairs_std<0, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
+      case 1: stencil_pairs_std<1, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
+      case 2: stencil_pairs_std<2, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
+      case 3: stencil_pairs_std<3, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
+      case 4: stencil_pairs_std<4, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
+      case 5: stencil_pairs_std<5, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
+      case 6: stencil_pairs_std<6, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
+      default: stencil_pairs_std<7, NL, 2 * TILE, VT, XT, AT>(hp, val, acc); break;
     }
   } else {
     const int len = st.len[t];
     const int32_t *off = st.off + 128 * t;
 #pragma unroll
-    for (int u = 0; u < NT; ++u) acc[u] = 0;
+    for (int v = 0; v < NL; ++v) acc[v][0] = acc[v][1] = 0;
     for (int j = 0; j < len; ++j) {
-      const AT v = static_cast<AT>(val[j]);
+      const AT w = static_cast<AT>(val[j]);
 #pragma unroll
-      for (int u = 0; u < NT; ++u) acc[u] += v * static_cast<AT>(hp[u * 8 * STENCIL_SUB + off[j]]);
+      for (int v = 0; v < NL; ++v)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) acc[v][r] += w * static_cast<AT>(hp[2 * v * TILE + off[j] + r * STENCIL_P2]);
     }
   }
   const AT dv = static_cast<AT>(st.dinv[t]);
 #pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    if (!active[u]) continue;
-    // x at the row itself: class t's sub-grid, one point inside the halo along each axis
-    const XT xi = hp[u * 8 * STENCIL_SUB + t * STENCIL_SUB + STENCIL_P1 + STENCIL_P2 + 1];
-    epi.apply_s(row[u], acc[u], pre[u], static_cast<AT>(xi), dv);
-  }
+  for (int v = 0; v < NL; ++v)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!active[v][r]) continue;
+      const XT xi = hp[2 * v * TILE + r * STENCIL_P2 + t * STENCIL_SUB + STENCIL_P1 + STENCIL_P2 + 1];
+      epi.apply_s(row[v][r], acc[v][r], pre[v][r], static_cast<AT>(xi), dv);
+    }
 }
 
 template <typename VT, typename XT, class Epi>

@@ -304,6 +304,12 @@ static DevSELL upload_sell(fvem_hierarchy *h, const HostCSR &A, int max_template
 // windows of 256, 384, 512, 768, 1024 and 4096 rows gave 2.34, 2.37, 2.40,
 // 2.40, 2.33 and 2.33 solves/s, and 64 (no sorting across slices) 2.03.
 constexpr int64_t ORDER_WINDOW = 512;
+// Operators small enough for the row-split kernel, where 16 lanes share a
+// row and a wavefront covers only 4 rows, keep 4096-row windows (2.41 ->
+// 2.44 solves/s on the same workload).
+static int64_t order_window(int64_t n_rows, int64_t small_rows) {
+  return small_rows >= 0 && n_rows <= small_rows ? 4096 : ORDER_WINDOW;
+}
 
 static void upload_lattice_level(fvem_hierarchy *h, Level &V, const HostCSR &A, HostLattice &lat,
                                  const std::vector<int32_t> &inv, int max_templates, bool codes, int64_t small_rows,
@@ -684,8 +690,8 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
   }
   kmem.reset();
 
-  // level order: rows sorted by length inside windows of ORDER_WINDOW rows;
-  // every level operator, transfer and per-DOF array is renumbered into it
+  // level order: rows sorted by length inside windows (order_window); every
+  // level operator, transfer and per-DOF array is renumbered into it
   std::vector<std::vector<int32_t>> inv(L);
   // a level below the coarsest takes the lattice layout when the
   // descriptor gives its lattice coordinates and enough of its rows are
@@ -709,7 +715,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
       inv[l] = inverse(lat[l].order, A[l].n_rows);
       continue;
     }
-    h->lv[l].order = window_order(A[l], ORDER_WINDOW);
+    h->lv[l].order = window_order(A[l], order_window(A[l].n_rows, small_rows));
     inv[l] = inverse(h->lv[l].order);
     A[l] = permute(A[l], h->lv[l].order, &inv[l]);
   }
@@ -772,7 +778,7 @@ static void build(fvem_hierarchy *h, const fvem_grid_desc *g, const fvem_options
       // transfers: rows sorted by length inside windows (own order), values
       // from templates where rows repeat; outputs are scattered back by rowmap
       auto transfer = [&](const HostCSR &T) {
-        const std::vector<int32_t> ord = window_order(T, ORDER_WINDOW);
+        const std::vector<int32_t> ord = window_order(T, order_window(T.n_rows, small_rows));
         const bool split = small_rows >= 0 && T.n_rows <= small_rows;
         DevSELL d = upload_sell(h, permute(T, ord, nullptr), max_templates, codes, s);
         d.rowmap = h->mem.upload(ord, s);

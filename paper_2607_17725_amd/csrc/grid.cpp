@@ -52,6 +52,63 @@ constexpr double kPlaneTol = 1e-12;
 // parallel planes meet; distinct vertices of the scenes stay above 1e-9
 constexpr double kVertTol = 1e-10;
 
+// Open-addressing map from 64-bit keys to int32 values, for the
+// sequential numbering passes (no per-entry allocation).  EMPTY is never a
+// key: callers map it elsewhere.
+struct FlatMap {
+  static constexpr uint64_t EMPTY = ~0ULL;
+  std::vector<uint64_t> key;
+  std::vector<int32_t> val;
+  uint64_t mask = 0;
+  size_t n = 0;
+  explicit FlatMap(size_t expect) {
+    size_t cap = 16;
+    while (cap < 2 * expect) cap <<= 1;
+    key.assign(cap, EMPTY);
+    val.assign(cap, -1);
+    mask = cap - 1;
+  }
+  static uint64_t spread(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    return x ^ (x >> 33);
+  }
+  // the value slot of k, inserted (value -1) when absent
+  int32_t *find_or_insert(uint64_t k, bool *inserted) {
+    if (2 * (n + 1) > key.size()) grow();
+    uint64_t i = spread(k) & mask;
+    while (key[i] != EMPTY) {
+      if (key[i] == k) {
+        *inserted = false;
+        return &val[i];
+      }
+      i = (i + 1) & mask;
+    }
+    key[i] = k;
+    ++n;
+    *inserted = true;
+    return &val[i];
+  }
+  void grow() {
+    std::vector<uint64_t> k2;
+    std::vector<int32_t> v2;
+    k2.swap(key);
+    v2.swap(val);
+    key.assign(2 * k2.size(), EMPTY);
+    val.assign(2 * k2.size(), -1);
+    mask = key.size() - 1;
+    for (size_t j = 0; j < k2.size(); ++j) {
+      if (k2[j] == EMPTY) continue;
+      uint64_t i = spread(k2[j]) & mask;
+      while (key[i] != EMPTY) i = (i + 1) & mask;
+      key[i] = k2[j];
+      val[i] = v2[j];
+    }
+  }
+};
+
 struct Node {
   Polyhedron poly;
   V3 n;
@@ -654,73 +711,111 @@ struct BuilderImpl {
         cy = std::move(nw);
       }
     }
-    // faces and edges (sequential, deterministic)
-    std::unordered_map<uint64_t, std::vector<int32_t>> fmap;
-    std::unordered_map<uint64_t, int32_t> emap;
+    // faces and edges, numbered in cell order (deterministic).  Per chunk of
+    // cells, each cycle's sorted vertex list, hash and unit normal are formed
+    // in parallel; the numbering itself is a sequential pass over flat maps.
+    FlatMap fhead(static_cast<size_t>(4 * nc + 16));   // cycle hash -> newest face with that hash
+    FlatMap emap(static_cast<size_t>(3 * M.X.size() + 16));
+    std::vector<int32_t> fnext;                         // older face with the same hash, or -1
+    std::vector<int32_t> fkey;                          // sorted vertex ids per face (offsets M.fptr)
     M.ctile.resize(nc);
     M.cplain.resize(nc);
     M.cside.resize(nc);
-    for (int64_t ci = 0; ci < nc; ++ci) {
-      M.ctile[ci] = fl[ci];
-      M.cplain[ci] = plain[ci];
-      M.cside[ci] = tiles[fl[ci]].type == 1 ? (1 << tiles[fl[ci]].s) : 0;
-      std::vector<int32_t> lv_verts, lv_edges;
-      for (auto &cy : cyc[ci]) {
-        std::vector<int32_t> key(cy);
-        std::sort(key.begin(), key.end());
-        uint64_t hk = 1469598103934665603ULL;
-        for (int32_t v : key) hk = (hk ^ static_cast<uint64_t>(v)) * 1099511628211ULL;
-        int32_t fid = -1;
-        auto &cand = fmap[hk];
-        for (int32_t f : cand) {
-          const int64_t m = M.fptr[f + 1] - M.fptr[f];
-          if (m != static_cast<int64_t>(key.size())) continue;
-          std::vector<int32_t> k2(M.fvert.begin() + M.fptr[f], M.fvert.begin() + M.fptr[f + 1]);
-          std::sort(k2.begin(), k2.end());
-          if (k2 == key) {
-            fid = f;
-            break;
+    constexpr int64_t CHUNK = 65536;
+    std::vector<int64_t> cbeg, kbeg;
+    std::vector<int32_t> kbuf;
+    std::vector<uint64_t> hbuf;
+    std::vector<V3> nbuf;
+    for (int64_t c0 = 0; c0 < nc; c0 += CHUNK) {
+      const int64_t c1 = std::min(nc, c0 + CHUNK);
+      cbeg.assign(c1 - c0 + 1, 0);
+      for (int64_t ci = c0; ci < c1; ++ci) cbeg[ci - c0 + 1] = cbeg[ci - c0] + static_cast<int64_t>(cyc[ci].size());
+      const int64_t ncy = cbeg.back();
+      kbeg.assign(ncy + 1, 0);
+      {
+        int64_t q = 0;
+        for (int64_t ci = c0; ci < c1; ++ci)
+          for (auto &cy : cyc[ci]) {
+            kbeg[q + 1] = kbeg[q] + static_cast<int64_t>(cy.size());
+            ++q;
           }
-        }
+      }
+      kbuf.resize(kbeg[ncy]);
+      hbuf.resize(ncy);
+      nbuf.resize(ncy);
+#pragma omp parallel for schedule(dynamic, 256)
+      for (int64_t ci = c0; ci < c1; ++ci) {
         std::vector<V3> P;
-        for (int32_t v : cy) P.push_back(M.X[v]);
-        V3 nvec = geo::area_vector(P);
-        nvec = (1.0 / norm(nvec)) * nvec;
-        if (fid < 0) {
-          fid = static_cast<int32_t>(M.fnormal.size());
-          cand.push_back(fid);
-          M.fvert.insert(M.fvert.end(), cy.begin(), cy.end());
-          M.fptr.push_back(static_cast<int64_t>(M.fvert.size()));
-          M.fnormal.push_back(nvec);
-          M.cface.push_back(fid);
-          M.corient.push_back(1);
-        } else {
-          M.cface.push_back(fid);
-          M.corient.push_back(dot(M.fnormal[fid], nvec) > 0 ? 1 : -1);
-        }
-        const size_t m = cy.size();
-        for (size_t i = 0; i < m; ++i) {
-          const int32_t a = cy[i], b = cy[(i + 1) % m];
-          if (std::find(lv_verts.begin(), lv_verts.end(), a) == lv_verts.end()) lv_verts.push_back(a);
-          const uint64_t ek = (static_cast<uint64_t>(std::min(a, b)) << 32) | static_cast<uint32_t>(std::max(a, b));
-          auto it = emap.find(ek);
-          int32_t e;
-          if (it == emap.end()) {
-            e = static_cast<int32_t>(M.edges.size());
-            emap.emplace(ek, e);
-            M.edges.push_back({std::min(a, b), std::max(a, b)});
-          } else {
-            e = it->second;
-          }
-          if (std::find(lv_edges.begin(), lv_edges.end(), e) == lv_edges.end()) lv_edges.push_back(e);
+        int64_t q = cbeg[ci - c0];
+        for (auto &cy : cyc[ci]) {
+          int32_t *key = kbuf.data() + kbeg[q];
+          std::copy(cy.begin(), cy.end(), key);
+          std::sort(key, key + cy.size());
+          uint64_t hk = 1469598103934665603ULL;
+          for (size_t t = 0; t < cy.size(); ++t) hk = (hk ^ static_cast<uint64_t>(key[t])) * 1099511628211ULL;
+          hbuf[q] = hk == FlatMap::EMPTY ? hk - 1 : hk;
+          P.clear();
+          for (int32_t v : cy) P.push_back(M.X[v]);
+          const V3 nvec = geo::area_vector(P);
+          nbuf[q] = (1.0 / norm(nvec)) * nvec;
+          ++q;
         }
       }
-      M.cfptr.push_back(static_cast<int64_t>(M.cface.size()));
-      M.cvert.insert(M.cvert.end(), lv_verts.begin(), lv_verts.end());
-      M.cvptr.push_back(static_cast<int64_t>(M.cvert.size()));
-      M.cedge.insert(M.cedge.end(), lv_edges.begin(), lv_edges.end());
-      M.ceptr.push_back(static_cast<int64_t>(M.cedge.size()));
-      std::vector<std::vector<int32_t>>().swap(cyc[ci]);
+      int64_t q = 0;
+      for (int64_t ci = c0; ci < c1; ++ci) {
+        M.ctile[ci] = fl[ci];
+        M.cplain[ci] = plain[ci];
+        M.cside[ci] = tiles[fl[ci]].type == 1 ? (1 << tiles[fl[ci]].s) : 0;
+        std::vector<int32_t> lv_verts, lv_edges;
+        for (auto &cy : cyc[ci]) {
+          const int32_t *key = kbuf.data() + kbeg[q];
+          const int64_t m = static_cast<int64_t>(cy.size());
+          const V3 nvec = nbuf[q];
+          bool fresh;
+          int32_t *head = fhead.find_or_insert(hbuf[q], &fresh);
+          int32_t fid = -1;
+          if (!fresh)
+            for (int32_t f = *head; f >= 0; f = fnext[f])
+              if (M.fptr[f + 1] - M.fptr[f] == m && std::equal(key, key + m, fkey.begin() + M.fptr[f])) {
+                fid = f;
+                break;
+              }
+          if (fid < 0) {
+            fid = static_cast<int32_t>(M.fnormal.size());
+            fnext.push_back(fresh ? -1 : *head);
+            *head = fid;
+            M.fvert.insert(M.fvert.end(), cy.begin(), cy.end());
+            fkey.insert(fkey.end(), key, key + m);
+            M.fptr.push_back(static_cast<int64_t>(M.fvert.size()));
+            M.fnormal.push_back(nvec);
+            M.cface.push_back(fid);
+            M.corient.push_back(1);
+          } else {
+            M.cface.push_back(fid);
+            M.corient.push_back(dot(M.fnormal[fid], nvec) > 0 ? 1 : -1);
+          }
+          for (int64_t i = 0; i < m; ++i) {
+            const int32_t a = cy[i], b = cy[(i + 1) % m];
+            if (std::find(lv_verts.begin(), lv_verts.end(), a) == lv_verts.end()) lv_verts.push_back(a);
+            const uint64_t ek = (static_cast<uint64_t>(std::min(a, b)) << 32) | static_cast<uint32_t>(std::max(a, b));
+            bool fresh_e;
+            int32_t *slot = emap.find_or_insert(ek, &fresh_e);
+            if (fresh_e) {
+              *slot = static_cast<int32_t>(M.edges.size());
+              M.edges.push_back({std::min(a, b), std::max(a, b)});
+            }
+            const int32_t e = *slot;
+            if (std::find(lv_edges.begin(), lv_edges.end(), e) == lv_edges.end()) lv_edges.push_back(e);
+          }
+          ++q;
+        }
+        M.cfptr.push_back(static_cast<int64_t>(M.cface.size()));
+        M.cvert.insert(M.cvert.end(), lv_verts.begin(), lv_verts.end());
+        M.cvptr.push_back(static_cast<int64_t>(M.cvert.size()));
+        M.cedge.insert(M.cedge.end(), lv_edges.begin(), lv_edges.end());
+        M.ceptr.push_back(static_cast<int64_t>(M.cedge.size()));
+        std::vector<std::vector<int32_t>>().swap(cyc[ci]);
+      }
     }
     M.cvol.resize(nc);
     M.ccen.resize(nc);
@@ -1149,31 +1244,49 @@ struct BuilderImpl {
       if (fi >= 0) frow[fi] = static_cast<int32_t>(r);
     }
     rp.assign(F.nfree + 1, 0);
-    ci.clear();
-    va.clear();
+    // each row is finished on its own (in parallel, in place), then the
+    // rows are concatenated in order
+#pragma omp parallel
+    {
+      std::vector<std::pair<int32_t, double>> ent;   // per-thread scratch
+#pragma omp for schedule(dynamic, 4096)
+      for (int64_t i = 0; i < F.nfree; ++i) {
+        auto &E = rows[frow[i]].e;
+        // weights at rounding level of the row's largest weight are zeros of
+        // the exact prolongation; dropped so that no coarse DOF keeps a
+        // numerically empty column
+        double wmax = 0;
+        for (auto &e : E) wmax = std::max(wmax, std::fabs(e.second));
+        ent.clear();
+        for (auto &e : E) {
+          const int32_t cj = C.free[C.perm[e.first]];
+          if (cj >= 0 && std::fabs(e.second) > 1e-13 * wmax) ent.push_back({cj, e.second});
+        }
+        std::sort(ent.begin(), ent.end());
+        // merge duplicates (a coarse DOF reached twice), written back over
+        // the row (never longer than it was)
+        size_t m = 0;
+        for (auto &e : ent) {
+          if (m > 0 && E[m - 1].first == e.first) E[m - 1].second += e.second;
+          else E[m++] = e;
+        }
+        E.resize(m);
+        rp[i + 1] = static_cast<int64_t>(m);
+      }
+    }
+    for (int64_t i = 0; i < F.nfree; ++i) rp[i + 1] += rp[i];
+    ci.resize(rp[F.nfree]);
+    va.resize(rp[F.nfree]);
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t i = 0; i < F.nfree; ++i) {
-      // weights at rounding level of the row's largest weight are zeros of
-      // the exact prolongation; dropped so that no coarse DOF keeps a
-      // numerically empty column
-      double wmax = 0;
-      for (auto &e : rows[frow[i]].e) wmax = std::max(wmax, std::fabs(e.second));
-      std::vector<std::pair<int32_t, double>> ent;
-      for (auto &e : rows[frow[i]].e) {
-        const int32_t cj = C.free[C.perm[e.first]];
-        if (cj >= 0 && std::fabs(e.second) > 1e-13 * wmax) ent.push_back({cj, e.second});
+      auto &E = rows[frow[i]].e;
+      int64_t q = rp[i];
+      for (auto &e : E) {
+        ci[q] = e.first;
+        va[q] = e.second;
+        ++q;
       }
-      std::sort(ent.begin(), ent.end());
-      // merge duplicates (a coarse DOF reached twice)
-      std::vector<std::pair<int32_t, double>> m;
-      for (auto &e : ent) {
-        if (!m.empty() && m.back().first == e.first) m.back().second += e.second;
-        else m.push_back(e);
-      }
-      for (auto &e : m) {
-        ci.push_back(e.first);
-        va.push_back(e.second);
-      }
-      rp[i + 1] = static_cast<int64_t>(ci.size());
+      std::vector<std::pair<int32_t, double>>().swap(E);   // freed here, in parallel
     }
   }
   std::unordered_map<uint64_t, int32_t> cedge_map;
@@ -1243,30 +1356,40 @@ struct BuilderImpl {
         std::vector<double> cmax(levels.back().nfree, 0.0);
         for (size_t q = 0; q < ci.size(); ++q) cmax[ci[q]] = std::max(cmax[ci[q]], std::fabs(va[q]));
         for (int64_t j = 0; j < levels.back().nfree; ++j) used[j] = cmax[j] > 1e-10;
-        // entries of unused columns are removed with the columns
-        std::vector<int64_t> rp2(rp.size(), 0);
-        std::vector<int32_t> ci2;
-        std::vector<double> va2;
-        for (size_t i = 0; i + 1 < rp.size(); ++i) {
-          for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
-            if (used[ci[q]]) {
-              ci2.push_back(ci[q]);
-              va2.push_back(va[q]);
-            }
-          rp2[i + 1] = static_cast<int64_t>(ci2.size());
-        }
-        rp.swap(rp2);
-        ci.swap(ci2);
-        va.swap(va2);
       }
       bool all = true;
       for (uint8_t u : used) all = all && u;
       if (!all) {
+        // entries of unused columns are removed with the columns (rows
+        // counted, then filled, in parallel)
+        const int64_t nr = static_cast<int64_t>(rp.size()) - 1;
+        std::vector<int64_t> rp2(rp.size(), 0);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < nr; ++i) {
+          int64_t c = 0;
+          for (int64_t q = rp[i]; q < rp[i + 1]; ++q) c += used[ci[q]];
+          rp2[i + 1] = c;
+        }
+        for (int64_t i = 0; i < nr; ++i) rp2[i + 1] += rp2[i];
         std::vector<int32_t> remap(levels.back().nfree, -1);
         int32_t q = 0;
         for (int64_t j = 0; j < levels.back().nfree; ++j)
           if (used[j]) remap[j] = q++;
-        for (int32_t &j : ci) j = remap[j];
+        std::vector<int32_t> ci2(rp2[nr]);
+        std::vector<double> va2(rp2[nr]);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < nr; ++i) {
+          int64_t o = rp2[i];
+          for (int64_t r = rp[i]; r < rp[i + 1]; ++r)
+            if (used[ci[r]]) {
+              ci2[o] = remap[ci[r]];
+              va2[o] = va[r];
+              ++o;
+            }
+        }
+        rp.swap(rp2);
+        ci.swap(ci2);
+        va.swap(va2);
         drop_unused(levels.back(), used);
       }
       progress("grid: level %zu has %lld cells and %lld DOFs", levels.size() - 1,

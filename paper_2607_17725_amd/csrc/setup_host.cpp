@@ -47,46 +47,84 @@ HostCSR assemble_blocks(int64_t n_rows, int64_t n_cols, const HostCells &rows, c
   A.n_rows = n_rows;
   A.n_cols = n_cols;
   A.rp.assign(n_rows + 1, 0);
-  // symbolic: sorted union of the column lists of the incident cells
-  std::vector<std::vector<int32_t>> pat(n_rows);
-#pragma omp parallel for schedule(dynamic, 4096)
-  for (int64_t i = 0; i < n_rows; ++i) {
-    std::vector<int32_t> &p = pat[i];
+  // symbolic: sorted union of the column lists of the incident cells (its
+  // length here, the list itself again in the numeric pass).  Each thread
+  // marks the columns it has seen for the current row in a stamp array over
+  // all columns, so only the distinct columns are sorted; the same array
+  // then maps a column to its position in the row.
+  auto pattern = [&](int64_t i, std::vector<int32_t> &p, std::vector<int32_t> &stamp) {
+    p.clear();
+    const int32_t mark = static_cast<int32_t>(i);
     for (int64_t k = iptr[i]; k < iptr[i + 1]; ++k) {
       int64_t c = icell[k];
-      for (int64_t q = cols.ptr[c]; q < cols.ptr[c + 1]; ++q)
-        if (cols.dof[q] >= 0) p.push_back(cols.dof[q]);
-    }
-    std::sort(p.begin(), p.end());
-    p.erase(std::unique(p.begin(), p.end()), p.end());
-  }
-  for (int64_t i = 0; i < n_rows; ++i) A.rp[i + 1] = A.rp[i] + static_cast<int64_t>(pat[i].size());
-  A.ci.resize(A.rp[n_rows]);
-  A.v.assign(A.rp[n_rows], 0.0);
-#pragma omp parallel for schedule(dynamic, 4096)
-  for (int64_t i = 0; i < n_rows; ++i) {
-    const std::vector<int32_t> &p = pat[i];
-    std::copy(p.begin(), p.end(), A.ci.begin() + A.rp[i]);
-    double *row = A.v.data() + A.rp[i];
-    // each entry sums its contributions in increasing order of value: rows
-    // whose contributions coincide (translated copies of one configuration)
-    // then assemble to bitwise equal values whatever the cell numbering
-    std::vector<std::pair<int64_t, double>> con;
-    for (int64_t k = iptr[i]; k < iptr[i + 1]; ++k) {
-      int64_t c = icell[k];
-      int32_t a = iloc[k];
-      int64_t m = cols.ptr[c + 1] - cols.ptr[c];
-      const double *blk = blocks.val.data() + blocks.off[c] + static_cast<int64_t>(a) * m;
-      for (int64_t b = 0; b < m; ++b) {
-        int32_t j = cols.dof[cols.ptr[c] + b];
-        if (j < 0) continue;
-        auto it = std::lower_bound(p.begin(), p.end(), j);
-        con.emplace_back(it - p.begin(), blk[b]);
+      for (int64_t q = cols.ptr[c]; q < cols.ptr[c + 1]; ++q) {
+        const int32_t j = cols.dof[q];
+        if (j >= 0 && stamp[j] != mark) {
+          stamp[j] = mark;
+          p.push_back(j);
+        }
       }
     }
-    std::sort(con.begin(), con.end());
-    for (const auto &e : con) row[e.first] += e.second;
-    std::vector<int32_t>().swap(pat[i]);
+    std::sort(p.begin(), p.end());
+  };
+#pragma omp parallel
+  {
+    std::vector<int32_t> p, stamp(n_cols, -1);
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n_rows; ++i) {
+      pattern(i, p, stamp);
+      A.rp[i + 1] = static_cast<int64_t>(p.size());
+    }
+  }
+  for (int64_t i = 0; i < n_rows; ++i) A.rp[i + 1] += A.rp[i];
+  A.ci.resize(A.rp[n_rows]);
+  A.v.assign(A.rp[n_rows], 0.0);
+#pragma omp parallel
+  {
+    std::vector<int32_t> p, stamp(n_cols, -1), pos(n_cols, 0);
+    std::vector<std::pair<int32_t, double>> con;   // (entry, value) in block order
+    std::vector<int32_t> start;                    // per entry: first slot of its contributions
+    std::vector<double> grouped;
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n_rows; ++i) {
+      pattern(i, p, stamp);
+      const int32_t len = static_cast<int32_t>(p.size());
+      for (int32_t e = 0; e < len; ++e) pos[p[e]] = e;
+      std::copy(p.begin(), p.end(), A.ci.begin() + A.rp[i]);
+      double *row = A.v.data() + A.rp[i];
+      // each entry sums its contributions in increasing order of value: rows
+      // whose contributions coincide (translated copies of one configuration)
+      // then assemble to bitwise equal values whatever the cell numbering.
+      // Contributions are grouped by entry (counting sort), then each
+      // entry's few values are sorted and summed.
+      con.clear();
+      for (int64_t k = iptr[i]; k < iptr[i + 1]; ++k) {
+        int64_t c = icell[k];
+        int32_t a = iloc[k];
+        int64_t m = cols.ptr[c + 1] - cols.ptr[c];
+        const double *blk = blocks.val.data() + blocks.off[c] + static_cast<int64_t>(a) * m;
+        for (int64_t b = 0; b < m; ++b) {
+          int32_t j = cols.dof[cols.ptr[c] + b];
+          if (j < 0) continue;
+          con.emplace_back(pos[j], blk[b]);
+        }
+      }
+      start.assign(len + 1, 0);
+      for (const auto &e : con) ++start[e.first + 1];
+      for (int32_t e = 0; e < len; ++e) start[e + 1] += start[e];
+      grouped.resize(con.size());
+      for (const auto &e : con) grouped[start[e.first]++] = e.second;
+      // start[e] is now the end of entry e's group; its begin is start[e - 1]
+      int32_t b0 = 0;
+      for (int32_t e = 0; e < len; ++e) {
+        const int32_t b1 = start[e];
+        std::sort(grouped.begin() + b0, grouped.begin() + b1);
+        double acc = 0.0;
+        for (int32_t t = b0; t < b1; ++t) acc += grouped[t];
+        row[e] = acc;
+        b0 = b1;
+      }
+    }
   }
   return A;
 }
@@ -314,6 +352,13 @@ HostCSR permute(const HostCSR &A, const std::vector<int32_t> &order, const std::
 
 namespace {
 
+inline uint64_t mix64(uint64_t z) {   // SplitMix64 finaliser
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
 // Template assignment of one value set.  quantum: relative rounding of the
 // hashed values (0: exact bits); tol: accepted deviation relative to the
 // row's largest entry.
@@ -340,15 +385,35 @@ void assign_templates(const HostCSR &A, const std::vector<int64_t> &ord, HostSEL
     }
     key[i] = h;
   }
-  std::unordered_map<uint64_t, std::pair<int64_t, int64_t>> first;   // key -> (first row, uses)
+  // key -> (first row, uses) in an open-addressing table; rows are visited
+  // in increasing order, so the first row seen is the smallest, and the
+  // table's slot a few rows ahead is fetched early
+  size_t cap = 16;
+  while (cap < 2 * static_cast<size_t>(S.n)) cap <<= 1;
+  const uint64_t mask = cap - 1;
+  std::vector<uint64_t> tkey(cap);
+  std::vector<int32_t> tfirst(cap, -1), tuses(cap, 0);
+  auto slot_of = [&](uint64_t k) {
+    uint64_t j = mix64(k) & mask;
+    while (tfirst[j] >= 0 && tkey[j] != k) j = (j + 1) & mask;
+    return j;
+  };
   for (int64_t i = 0; i < S.n; ++i) {
-    auto it = first.find(key[i]);
-    if (it == first.end()) first.emplace(key[i], std::make_pair(i, int64_t(1)));
-    else it->second.second++;
+    if (i + 16 < S.n) {
+      const uint64_t ja = mix64(key[i + 16]) & mask;
+      __builtin_prefetch(&tkey[ja]);
+      __builtin_prefetch(&tfirst[ja]);
+    }
+    const uint64_t j = slot_of(key[i]);
+    if (tfirst[j] < 0) {
+      tkey[j] = key[i];
+      tfirst[j] = static_cast<int32_t>(i);
+    }
+    ++tuses[j];
   }
   std::vector<std::pair<int64_t, uint64_t>> popular;   // (uses, key)
-  for (const auto &kv : first)
-    if (kv.second.second >= min_uses) popular.emplace_back(kv.second.second, kv.first);
+  for (size_t j = 0; j < cap; ++j)
+    if (tfirst[j] >= 0 && tuses[j] >= min_uses) popular.emplace_back(tuses[j], tkey[j]);
   std::sort(popular.begin(), popular.end(), [](const auto &x, const auto &y) {
     return x.first > y.first || (x.first == y.first && x.second < y.second);
   });
@@ -356,7 +421,7 @@ void assign_templates(const HostCSR &A, const std::vector<int64_t> &ord, HostSEL
   std::unordered_map<uint64_t, int32_t> tindex;
   std::vector<int64_t> trow;
   for (const auto &pk : popular) {
-    const int64_t r = first[pk.second].first;
+    const int64_t r = tfirst[slot_of(pk.second)];
     tindex.emplace(pk.second, V.nt++);
     trow.push_back(r);
     V.tw = std::max(V.tw, (S.rl[r] + 3) & ~3);
@@ -524,13 +589,6 @@ HostCSR from_sell(const HostSELL &S) {
 }
 
 namespace {
-
-inline uint64_t mix64(uint64_t z) {   // SplitMix64 finaliser
-  z += 0x9E3779B97F4A7C15ULL;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
 
 inline uint64_t morton3(uint32_t a, uint32_t b, uint32_t c) {
   uint64_t m = 0;

@@ -715,7 +715,13 @@ struct BuilderImpl {
     // cells, each cycle's sorted vertex list, hash and unit normal are formed
     // in parallel; the numbering itself is a sequential pass over flat maps.
     FlatMap fhead(static_cast<size_t>(4 * nc + 16));   // cycle hash -> newest face with that hash
-    FlatMap emap(static_cast<size_t>(3 * M.X.size() + 16));
+    // edges by their lower vertex: a few inline (upper vertex, edge) slots
+    // per vertex, which neighbouring cells reach in nearby memory, and a
+    // map for vertices with more edges than slots
+    constexpr int EDGE_SLOTS = 6;
+    std::vector<std::array<int32_t, 2 * EDGE_SLOTS>> vadj(M.X.size());
+    for (auto &sl : vadj) sl.fill(-1);
+    FlatMap emap(1024);
     std::vector<int32_t> fnext;                         // older face with the same hash, or -1
     std::vector<int32_t> fkey;                          // sorted vertex ids per face (offsets M.fptr)
     M.ctile.resize(nc);
@@ -798,13 +804,31 @@ struct BuilderImpl {
             const int32_t a = cy[i], b = cy[(i + 1) % m];
             if (std::find(lv_verts.begin(), lv_verts.end(), a) == lv_verts.end()) lv_verts.push_back(a);
             const uint64_t ek = (static_cast<uint64_t>(std::min(a, b)) << 32) | static_cast<uint32_t>(std::max(a, b));
-            bool fresh_e;
-            int32_t *slot = emap.find_or_insert(ek, &fresh_e);
-            if (fresh_e) {
-              *slot = static_cast<int32_t>(M.edges.size());
-              M.edges.push_back({std::min(a, b), std::max(a, b)});
+            const int32_t lo = std::min(a, b), hi = std::max(a, b);
+            int32_t e = -1;
+            auto &sl = vadj[lo];
+            int t = 0;
+            for (; t < EDGE_SLOTS && sl[2 * t] >= 0; ++t)
+              if (sl[2 * t] == hi) {
+                e = sl[2 * t + 1];
+                break;
+              }
+            if (e < 0) {
+              int32_t *slot = nullptr;
+              bool fresh_e = true;
+              if (t == EDGE_SLOTS) slot = emap.find_or_insert(ek, &fresh_e);
+              if (fresh_e) {
+                e = static_cast<int32_t>(M.edges.size());
+                M.edges.push_back({lo, hi});
+                if (slot) *slot = e;
+                else {
+                  sl[2 * t] = hi;
+                  sl[2 * t + 1] = e;
+                }
+              } else {
+                e = *slot;
+              }
             }
-            const int32_t e = *slot;
             if (std::find(lv_edges.begin(), lv_edges.end(), e) == lv_edges.end()) lv_edges.push_back(e);
           }
           ++q;

@@ -20,6 +20,7 @@
 //  * conforming faces are the overlaps of coplanar opposite facets of
 //    neighbouring cells of the full (fluid + solid) tiling, with T-junction
 //    vertices inserted; coarse DOFs the prolongation never uses are dropped.
+#include <parallel/algorithm>
 #include "grid.hpp"
 #include "progress.hpp"
 
@@ -956,7 +957,9 @@ struct BuilderImpl {
       const uint64_t mo = morton(i, j, kk);
       key[r] = {{((mo >> 6) << 2) | static_cast<uint64_t>(raw_kind(M, r)), mo}, static_cast<int32_t>(r)};
     }
-    std::sort(key.begin(), key.end());
+    // keys are unique (they end in the raw id), so the parallel sort gives
+    // the serial order
+    __gnu_parallel::sort(key.begin(), key.end());
     lv.perm.assign(n, -1);
     for (int64_t q = 0; q < n; ++q) lv.perm[key[q].second] = static_cast<int32_t>(q);
     // Dirichlet: DOFs supported on z = 1
